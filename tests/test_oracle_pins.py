@@ -1,0 +1,462 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix.
+
+None of these retypes the oracle's own formulas: each compares against a worked
+example printed in the paper, a library routine, a closed form, an invariant,
+or brute-force enumeration on tiny inputs.
+"""
+
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import codes
+from workloads.perms import check_permutations
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Philox (noise)
+
+def _numpy_philox_block(ctr, key):
+    """numpy's Philox advances its 256-bit counter before producing a block, so
+    the block for counter c is the first output of a generator started at c - 1."""
+    c = [int(x) for x in ctr]
+    total = c[0] | (c[1] << 64) | (c[2] << 128) | (c[3] << 192)
+    total = (total - 1) % (1 << 256)
+    start = [(total >> (64 * i)) & ((1 << 64) - 1) for i in range(4)]
+    bg = np.random.Philox(counter=np.array(start, dtype=np.uint64),
+                          key=np.array([int(k) for k in key], dtype=np.uint64))
+    return bg.random_raw(4)
+
+
+@pytest.mark.parametrize("ctr,key", [
+    ([0, 0, 0, 0], [0, 0]),
+    ([1, 0, 0, 0], [0, 0]),
+    ([12345, 17, 0, 0], [1, 0]),
+    ([2**64 - 1, 5, 3, 1], [0xDEADBEEF, 42]),
+    ([7, 2**63, 0, 2**64 - 1], [2**64 - 1, 2**64 - 1]),
+])
+def test_philox_matches_numpy(ctr, key):
+    np.testing.assert_array_equal(oracle.philox4x64_10(ctr, key), _numpy_philox_block(ctr, key))
+
+
+@pytest.mark.parametrize("p", [0.01, 0.02, 0.03, 0.04, 0.05, 0.06, 0.08, 0.1, 0.5])
+def test_thresholds_equal_exact_floor(p):
+    """The double-precision thresholds floor(k p/3 2^32) equal the exact rational
+    floor for the error rates used (so no rounding ambiguity exists there)."""
+    for k in (1, 2, 3):
+        exact = (Fraction(k) * Fraction(p) / 3 * 2**32).__floor__()
+        approx = int(np.floor(k * (p / 3.0) * 4294967296.0))
+        assert exact == approx
+
+
+def test_sampler_against_numpy_philox_and_matmul():
+    """Errors re-derived from numpy's Philox stream with exact rational thresholds,
+    syndromes from an integer matrix product."""
+    code = codes.bb72()
+    seed, p, shot0, shots = 1, 0.05, 1000, 40
+    ex, ez, sx, sz = oracle.sample(code.hx, code.hz, seed, p, shot0, shots)
+    n = code.n
+    t = [(Fraction(k) * Fraction(p) / 3 * 2**32).__floor__() for k in (1, 2, 3)]
+    bx = np.zeros((shots, n), np.uint8)
+    bz = np.zeros((shots, n), np.uint8)
+    for s in range(shots):
+        for b in range((n + 7) // 8):
+            out = _numpy_philox_block([shot0 + s, b, 0, 0], [seed, 0])
+            for sub in range(8):
+                q = 8 * b + sub
+                if q >= n:
+                    break
+                u = (int(out[sub // 2]) >> (32 * (sub % 2))) & 0xFFFFFFFF
+                if u < t[0]:
+                    bx[s, q] = 1
+                elif u < t[1]:
+                    bx[s, q] = bz[s, q] = 1
+                elif u < t[2]:
+                    bz[s, q] = 1
+    np.testing.assert_array_equal(oracle.unpack(ex, n), bx)
+    np.testing.assert_array_equal(oracle.unpack(ez, n), bz)
+    np.testing.assert_array_equal(oracle.unpack(sx, code.hx.shape[0]),
+                                  (bz.astype(np.int64) @ code.hx.T.astype(np.int64)) % 2)
+    np.testing.assert_array_equal(oracle.unpack(sz, code.hz.shape[0]),
+                                  (bx.astype(np.int64) @ code.hz.T.astype(np.int64)) % 2)
+
+
+def test_sampler_frequencies():
+    """X-only, Y and Z-only frequencies each p/3 within 5 binomial sigmas."""
+    code = codes.bb144()
+    p, shots = 0.06, 20000
+    ex, ez, _, _ = oracle.sample(code.hx, code.hz, 7, p, 0, shots)
+    bx = oracle.unpack(ex, code.n).astype(bool)
+    bz = oracle.unpack(ez, code.n).astype(bool)
+    N = bx.size
+    for cnt in ((bx & ~bz).sum(), (bx & bz).sum(), (~bx & bz).sum()):
+        mean = N * p / 3
+        assert abs(cnt - mean) < 5 * np.sqrt(mean * (1 - p / 3))
+
+
+# ------------------------------------------------------------------ codes and GF(2)
+
+@pytest.mark.parametrize("factory,k", [(codes.bb72, 12), (codes.bb144, 12), (codes.bb288, 12),
+                                       (codes.qc882, 24), (codes.steane7, 1),
+                                       (codes.surface13, 1), (codes.toric18, 2)])
+def test_code_dimension(factory, k):
+    """k = n - rank H_X - rank H_Z equals the published [[n, k]] (Section IV)."""
+    c = factory()
+    assert not ((c.hx.astype(np.int64) @ c.hz.T.astype(np.int64)) % 2).any()
+    assert c.n - oracle.rank(c.hx) - oracle.rank(c.hz) == k
+
+
+def _span(h):
+    """All vectors of the row space by enumeration (tiny h only)."""
+    rows = [r.astype(np.uint8) for r in h]
+    out = set()
+    for coeffs in itertools.product([0, 1], repeat=len(rows)):
+        v = np.zeros(h.shape[1], np.uint8)
+        for c, r in zip(coeffs, rows):
+            if c:
+                v ^= r
+        out.add(v.tobytes())
+    return out
+
+
+def test_rank_and_rowspace_brute_force():
+    rng = np.random.default_rng(3)
+    for _ in range(30):
+        m, n = rng.integers(1, 7), rng.integers(2, 10)
+        h = (rng.random((m, n)) < 0.4).astype(np.uint8)
+        span = _span(h)
+        assert oracle.rank(h) == int(np.log2(len(span)))
+        q = (rng.random((12, n)) < 0.5).astype(np.uint8)
+        mem = oracle.in_rowspace(h, q)
+        for row, got in zip(q, mem):
+            assert got == (row.tobytes() in span)
+
+
+# ------------------------------------------------------------------ Algorithm 2
+
+def _read_fig2():
+    rec = {}
+    with open(os.path.join(GOLDEN, "fig2_subtrees.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            tok = line.split()
+            rec.setdefault(tok[0], []).append(tok[1:])
+    h = np.array([[int(ch) for ch in row] for row in rec["H"][0]], np.uint8)
+    perm = [int(x) for x in rec["perm"][0]]
+    cs = [int(x) for x in rec["check_sets"][0]]
+    subs = {int(t[0]): [int(x) for x in t[1:]] for t in rec["subtree"]}
+    return h, perm, cs, subs
+
+
+def test_fig2_worked_example():
+    h, perm, cs_expect, subs = _read_fig2()
+    np.testing.assert_array_equal(h, codes.fig2_matrix())
+    cs, order, ns = oracle.subtrees(h, perm)
+    assert list(cs) == cs_expect
+    assert ns == len(subs)
+    lists = oracle.subtree_lists(h, perm)
+    for s, rows in subs.items():
+        assert lists[s - 1] == rows
+
+
+def _check_subtree_invariants(h, perm):
+    m, n = h.shape
+    cs, order, ns = oracle.subtrees(h, perm)
+    assert sorted(order.tolist()) == list(range(m))           # every check once
+    assert set(cs.tolist()) == set(range(1, ns + 1))           # a partition
+    w = int(h.sum(axis=1).max())
+    lists = oracle.subtree_lists(h, perm)
+    for s, rows in enumerate(lists, start=1):
+        sub = h[rows]
+        covered = np.nonzero(sub.any(axis=0))[0]
+        # acyclic and connected: a tree has #vars = sum(deg) - (#checks - 1)
+        assert covered.size == int(sub.sum()) - (len(rows) - 1)
+        # every prefix of the acceptance order is connected (BFS growth)
+        seen = set(np.nonzero(h[rows[0]])[0])
+        for r in rows[1:]:
+            vs = set(np.nonzero(h[r])[0])
+            assert len(vs & seen) == 1
+            seen |= vs
+        # maximality: a check unassigned while s was built (assigned later) that
+        # touches s's variables touches at least two of them
+        cov = set(covered.tolist())
+        for c in range(m):
+            if cs[c] > s:
+                inter = len(set(np.nonzero(h[c])[0]) & cov)
+                assert inter == 0 or inter >= 2
+        # Lemma 1: |t| <= (|V_v| - 1) / (w - 1)
+        assert len(rows) <= (n - 1) / (w - 1)
+    # the root of each subtree is the first unassigned check in pi order
+    roots = [rows[0] for rows in lists]
+    pos = {c: i for i, c in enumerate(perm)}
+    assert roots == sorted(roots, key=lambda c: pos[c])
+
+
+@pytest.mark.parametrize("factory", [codes.bb72, codes.bb144, codes.bb288, codes.qc882])
+def test_subtree_invariants(factory):
+    c = factory()
+    for h in (c.hx, c.hz):
+        perms = check_permutations(h.shape[0], 3, seed=11)
+        for perm in perms:
+            _check_subtree_invariants(h, perm)
+
+
+def test_bases_subtree_mode_and_ramp():
+    c = codes.bb144()
+    perms = check_permutations(72, 8, seed=0)
+    bp, rows = oracle.build_bases(c.hx, "subtrees", 16, perms)
+    sets = [frozenset(rows[bp[l]:bp[l + 1]].tolist()) for l in range(16)]
+    assert len(set(sets)) == 16                                # distinct row sets
+    all_subtrees = [frozenset(r) for k in range(8) for r in oracle.subtree_lists(c.hx, perms[k])]
+    assert all(s in all_subtrees for s in sets)               # each is a maximal subtree
+    c3 = codes.bb288()
+    perms3 = check_permutations(144, 32, seed=0)
+    bp3, rows3 = oracle.build_bases(c3.hx, "ramp", 32, perms3)
+    sizes = np.diff(bp3)
+    assert sizes[0] == 0 and sizes[-1] == 144
+    assert all(sizes[l] == round(l * 144 / 31) for l in range(32))
+    assert sorted(rows3[bp3[-2]:bp3[-1]].tolist()) == list(range(144))
+
+
+# ------------------------------------------------------------------ BP closed forms
+
+def _one_basis(h, rows):
+    return np.array([0, len(rows)], np.int32), np.array(rows, np.int32)
+
+
+@pytest.mark.parametrize("schedule", [oracle.FLOODING])
+@pytest.mark.parametrize("mu,alpha,rmax", [(2.5, 0.75, 65536.0), (3.0, 0.875, 1.0)])
+def test_iteration_one_closed_form(schedule, mu, alpha, rmax):
+    """After one flooding iteration from uniform mu > 0 every check message is
+    (-1)^{s_j} * min(alpha * mu, rmax), so P_i = mu + that summed over N(i)."""
+    c = codes.bb72()
+    h = c.hz
+    bp, rows = _one_basis(h, [0, 5, 7])
+    rng = np.random.default_rng(0)
+    sb = (rng.random((6, h.shape[0])) < 0.3).astype(np.uint8)
+    syn = oracle.pack(sb)
+    res = oracle.decode(h, bp, rows, syn, np.full(h.shape[1], mu), T=1, schedule=schedule,
+                        alpha=alpha, rmax=rmax, fixed_T=True, want_llr=True)
+    haug = np.concatenate([h, h[rows]], axis=0).astype(np.int64)
+    saug = np.concatenate([sb, sb[:, rows]], axis=1).astype(np.int64)
+    mag = min(alpha * mu, rmax)
+    expect = mu + mag * ((1 - 2 * saug) @ haug)
+    np.testing.assert_allclose(res.llr[:, 0, :], expect, rtol=0, atol=1e-12)
+
+
+def test_hand_example_schedules():
+    """Two weight-2 checks sharing variable 1, s = (1, 0), mu = (2, 3, 4), alpha 1/2.
+    By hand, one iteration gives
+      flooding: r00 = -1.5, r01 = -1, r11 = 2, r12 = 1.5  -> P = (0.5, 4, 5.5)
+      serial:   r00 = -1.5, r01 = -1, then q11 = 3 - 1 = 2: r11 = 2, r12 = 1 -> P = (0.5, 4, 5)."""
+    h = np.array([[1, 1, 0], [0, 1, 1]], np.uint8)
+    syn = oracle.pack(np.array([[1, 0]], np.uint8))
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    mu = np.array([2.0, 3.0, 4.0])
+    fl = oracle.decode(h, bp, rows, syn, mu, T=1, schedule=oracle.FLOODING, alpha=0.5,
+                       fixed_T=True, want_llr=True)
+    se = oracle.decode(h, bp, rows, syn, mu, T=1, schedule=oracle.LAYERED, alpha=0.5,
+                       fixed_T=True, want_llr=True)
+    np.testing.assert_array_equal(fl.llr[0, 0], [0.5, 4.0, 5.5])
+    np.testing.assert_array_equal(se.llr[0, 0], [0.5, 4.0, 5.0])
+
+
+def _random_tree(rng, n_checks, wmin=2, wmax=4):
+    """Random tree-shaped Tanner graph: each new check shares exactly one existing variable."""
+    rows = []
+    nvar = 0
+    for j in range(n_checks):
+        w = int(rng.integers(wmin, wmax + 1))
+        if j == 0:
+            vs = list(range(w))
+            nvar = w
+        else:
+            anchor = int(rng.integers(0, nvar))
+            vs = [anchor] + list(range(nvar, nvar + w - 1))
+            nvar += w - 1
+        rows.append(vs)
+    h = np.zeros((n_checks, nvar), np.uint8)
+    for j, vs in enumerate(rows):
+        h[j, vs] = 1
+    perm = rng.permutation(nvar)     # scramble variable labels
+    return h[:, perm]
+
+
+def _brute_posteriors(h, s, mu, mode):
+    """Exact LLRs ln P(e_i=0|s)/P(e_i=1|s) ('sum') or min-cost differences ('min')."""
+    m, n = h.shape
+    E = np.array(list(itertools.product([0, 1], repeat=n)), np.int64)
+    ok = ((E @ h.T.astype(np.int64)) % 2 == s[None, :]).all(axis=1)
+    E = E[ok]
+    cost = E @ mu                     # -log-likelihood up to a constant
+    out = np.zeros(n)
+    for i in range(n):
+        c0, c1 = cost[E[:, i] == 0], cost[E[:, i] == 1]
+        if mode == "sum":
+            a0 = np.log(np.exp(-(c0 - cost.min())).sum())
+            a1 = np.log(np.exp(-(c1 - cost.min())).sum())
+            out[i] = a0 - a1
+        else:
+            out[i] = c1.min() - c0.min()
+    return out
+
+
+@pytest.mark.parametrize("schedule", [oracle.FLOODING, oracle.LAYERED])
+def test_sum_product_exact_on_trees(schedule):
+    """BP is exact on cycle-free graphs (Section III-A): the sum-product posteriors
+    equal brute-force marginals."""
+    rng = np.random.default_rng(5)
+    for trial in range(12):
+        h = _random_tree(rng, int(rng.integers(2, 5)))
+        n = h.shape[1]
+        if n > 14:
+            continue
+        s = rng.integers(0, 2, h.shape[0]).astype(np.int64)
+        mu = rng.uniform(-1.0, 3.0, n)
+        res = oracle.decode(h, np.array([0, 0], np.int32), np.array([], np.int32),
+                            oracle.pack(s[None, :].astype(np.uint8)), mu, T=30, schedule=schedule,
+                            rule=oracle.SPA, fixed_T=True, want_llr=True)
+        np.testing.assert_allclose(res.llr[0, 0], _brute_posteriors(h, s, mu, "sum"),
+                                   rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("schedule", [oracle.FLOODING, oracle.LAYERED])
+def test_min_sum_is_min_cost_on_trees(schedule):
+    """Min-sum with alpha = 1 on a tree computes min-cost differences exactly."""
+    rng = np.random.default_rng(6)
+    for trial in range(12):
+        h = _random_tree(rng, int(rng.integers(2, 5)))
+        n = h.shape[1]
+        if n > 14:
+            continue
+        s = rng.integers(0, 2, h.shape[0]).astype(np.int64)
+        mu = rng.uniform(0.5, 3.0, n)
+        res = oracle.decode(h, np.array([0, 0], np.int32), np.array([], np.int32),
+                            oracle.pack(s[None, :].astype(np.uint8)), mu, T=30, schedule=schedule,
+                            rule=oracle.NMS, alpha=1.0, fixed_T=True, want_llr=True)
+        np.testing.assert_allclose(res.llr[0, 0], _brute_posteriors(h, s, mu, "min"),
+                                   rtol=1e-12, atol=1e-12)
+
+
+def test_tree_from_a_code_subtree():
+    """H_t of a maximal subtree, restricted to its variables, is a tree: sum-product on
+    it is exact (the structure Section III-A builds on)."""
+    c = codes.bb72()
+    lists = oracle.subtree_lists(c.hx, np.arange(36))
+    rows = lists[0][:2]     # a prefix of the acceptance order is itself a tree
+    sub = c.hx[rows]
+    h = sub[:, sub.any(axis=0)]
+    rng = np.random.default_rng(9)
+    s = rng.integers(0, 2, h.shape[0]).astype(np.int64)
+    mu = rng.uniform(0.5, 2.0, h.shape[1])
+    res = oracle.decode(h, np.array([0, 0], np.int32), np.array([], np.int32),
+                        oracle.pack(s[None, :].astype(np.uint8)), mu, T=10, rule=oracle.SPA,
+                        fixed_T=True, want_llr=True)
+    np.testing.assert_allclose(res.llr[0, 0], _brute_posteriors(h, s, mu, "sum"), atol=1e-9)
+
+
+def test_zero_syndrome_stops_at_iteration_zero():
+    c = codes.bb72()
+    bp, rows = _one_basis(c.hx, [1, 2])
+    res = oracle.decode(c.hx, bp, rows, np.zeros((3, 1), np.uint64), np.full(72, 2.0), T=20)
+    assert (res.K == 0).all() and res.conv.all() and (res.corr == 0).all() and (res.chosen == 0).all()
+
+
+# ------------------------------------------------------------------ list decision
+
+def test_decision_rules_worked_example():
+    """List with candidate A (weight 2) from bases 0, 2, 3 and B (weight 1) from basis 1:
+    least weight picks B (basis 1); FWS scores A 3/3 = 1 > B 1/2 and picks basis 0."""
+    A = oracle.pack(np.array([[1, 1, 0, 0]], np.uint8))[0]
+    B = oracle.pack(np.array([[0, 0, 1, 0]], np.uint8))[0]
+    cand = np.array([[A, B, A, A]], np.uint64)
+    conv = np.array([[1, 1, 1, 1]], bool)
+    assert oracle.select(cand, conv, oracle.MIN_WEIGHT)[0] == 1
+    assert oracle.select(cand, conv, oracle.FWS)[0] == 0
+    # ties: equal weights -> smaller basis index; nothing converged -> -1
+    C = oracle.pack(np.array([[0, 1, 0, 0]], np.uint8))[0]
+    cand2 = np.array([[A, C, B, C]], np.uint64)
+    assert oracle.select(cand2, np.array([[0, 1, 1, 1]], bool), oracle.MIN_WEIGHT)[0] == 1
+    # FWS: C twice (2/2 = 1) beats B once (1/2)
+    assert oracle.select(cand2, np.array([[0, 1, 1, 1]], bool), oracle.FWS)[0] == 1
+    assert oracle.select(cand2, np.zeros((1, 4), bool), oracle.FWS)[0] == -1
+    assert oracle.select(cand2, np.zeros((1, 4), bool), oracle.MIN_WEIGHT)[0] == -1
+
+
+# ------------------------------------------------------------------ small codes, brute force
+
+def _stabilizer_group(h):
+    return _span(h)
+
+
+@pytest.mark.parametrize("factory", [codes.steane7, codes.surface13, codes.toric18])
+def test_small_codes_against_brute_force(factory):
+    """On n <= 18: every accepted candidate meets its syndrome; the chosen weight is at
+    least the brute-force minimum weight; failure flags equal stabilizer-group
+    membership of the residual."""
+    c = factory()
+    n = c.n
+    perms_x = check_permutations(c.hx.shape[0], 4, seed=2)
+    perms_z = check_permutations(c.hz.shape[0], 4, seed=2)
+    ex, ez, sx, sz = oracle.sample(c.hx, c.hz, 3, 0.12, 0, 300)
+    mu = np.full(n, oracle.prior_llr(0.12))
+    all_e = np.array(list(itertools.product([0, 1], repeat=n)), np.int64)
+    for h, stab, perms, syn, err in ((c.hz, c.hx, perms_z, sz, ex), (c.hx, c.hz, perms_x, sx, ez)):
+        L = 2
+        bp, rows = oracle.build_bases(h, "ramp", L, perms)
+        res = oracle.decode(h, bp, rows, syn, mu, T=15, alpha=0.875)
+        sb = oracle.unpack(syn, h.shape[0]).astype(np.int64)
+        cb = oracle.unpack(res.cand, n).astype(np.int64)
+        hh = h.astype(np.int64)
+        for s in range(syn.shape[0]):
+            for l in range(L):
+                if res.conv[s, l]:
+                    np.testing.assert_array_equal((cb[s, l] @ hh.T) % 2, sb[s])
+        synd_all = (all_e @ hh.T) % 2
+        group = _stabilizer_group(stab)
+        fails = oracle.failures(stab, err, res.corr)
+        eb = oracle.unpack(err, n)
+        corr_b = oracle.unpack(res.corr, n)
+        for s in range(syn.shape[0]):
+            if res.chosen[s] >= 0:
+                wmin = all_e[(synd_all == sb[s]).all(axis=1)].sum(axis=1).min()
+                assert corr_b[s].sum() >= wmin
+            resid = (eb[s] ^ corr_b[s]).astype(np.uint8)
+            assert fails[s] == (resid.tobytes() not in group)
+
+
+def test_failure_flags_known_cases():
+    """Steane: a stabilizer residual is no failure; the all-ones logical is one."""
+    c = codes.steane7()
+    err = oracle.pack(np.array([[1, 0, 1, 0, 1, 0, 1], [1, 1, 1, 1, 1, 1, 1], [0] * 7], np.uint8))
+    corr = oracle.pack(np.zeros((3, 7), np.uint8))
+    np.testing.assert_array_equal(oracle.failures(c.hx, err, corr), [False, True, False])
+
+
+def test_general_row_not_in_rowspace_rejected():
+    c = codes.steane7()
+    bp = np.array([0, 1], np.int32)
+    rows = np.array([-1], np.int32)
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.decode(c.hx, bp, rows, np.zeros((1, 1), np.uint64), np.full(7, 2.0), T=3,
+                      explicit={0: np.array([1, 0, 0, 0, 0, 0, 0], np.uint8)})
+    assert ei.value.status == oracle.ORC_ENOTINROWSPACE
+    # a sum of two rows is accepted and its syndrome bit is the sum of theirs
+    row = (c.hx[0] ^ c.hx[1]).astype(np.uint8)
+    res = oracle.decode(c.hx, bp, rows, oracle.pack(np.array([[1, 0, 0]], np.uint8)),
+                        np.full(7, 2.0), T=1, fixed_T=True, want_llr=True, alpha=1.0,
+                        explicit={0: row})
+    haug = np.concatenate([c.hx, row[None]], 0).astype(np.int64)
+    saug = np.array([1, 0, 0, 1])
+    np.testing.assert_allclose(res.llr[0, 0], 2.0 + 2.0 * ((1 - 2 * saug) @ haug))
+
+
+def test_f32_build_is_single_precision():
+    assert oracle._lib("f32").orc_real_bytes() == 4
+    assert oracle._lib("f64").orc_real_bytes() == 8
