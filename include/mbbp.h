@@ -1,0 +1,218 @@
+/*
+ * mbbp.h -- C ABI of the MI355X (gfx950) multiple-bases BP list decoder (MBBP-LD)
+ * for CSS quantum LDPC codes.
+ *
+ * Method (Sections II-III of the MBBP-LD paper):
+ *   - A CSS code has parity-check matrices H_X, H_Z with H_X H_Z^T = 0
+ *     (Section II-A).  X errors e_X are seen by H_Z, Z errors e_Z by H_X.
+ *   - L redundant representations [H; H_t] of each matrix are built from maximal
+ *     cycle-free subtrees of the Tanner graph (Algorithm 2, eq. (3)).
+ *   - BP (normalized min-sum, eqs. (1)-(2), or sum-product) runs on every
+ *     representation; converged estimates form a list (Algorithm 1) from which a
+ *     decision rule picks one (Section III-B: least weight, or FWS); if nothing
+ *     converges the estimate is all-zero and the shot is a failure.
+ *
+ * Naming: everything is named by the ERROR TYPE it concerns.
+ *   part X : e_X, syndrome s_X = H_Z e_X (m_Z bits), decoded on representations
+ *            of H_Z, correction corr_x; logical failure iff e_X ^ corr_x is not in
+ *            the row space of H_X.
+ *   part Z : e_Z, s_Z = H_X e_Z (m_X bits), representations of H_X, corr_z;
+ *            failure iff e_Z ^ corr_z is not in the row space of H_Z.
+ *
+ * Layouts: bit vectors are uint64 words, bit i in word i/64 at position i%64
+ * (LSB first); per-shot arrays are [shots][words] row-major.  Device pointers
+ * are HIP device memory owned by the caller; host pointers are plain memory
+ * owned by the caller.  All device work is enqueued on the given hipStream_t
+ * (passed as void*, NULL = default stream) and is asynchronous; outputs are
+ * valid once the stream has been synchronised.
+ *
+ * Errors: every call returns mbbp_status; no C++ exception crosses the ABI.
+ * Arguments are validated on the host before anything is enqueued, and on
+ * error no output is written.  mbbp_last_error() gives a thread-local message
+ * for the most recent non-OK status.  A device fault surfaces as MBBP_EDEVICE.
+ */
+#ifndef MBBP_H
+#define MBBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbbp_ctx mbbp_ctx;
+
+typedef enum {
+    MBBP_OK = 0,
+    MBBP_EINVAL = -1,          /* bad argument (shape, pointer, range, H_X H_Z^T != 0, ...) */
+    MBBP_ENOTINROWSPACE = -2,  /* an explicit appended row is not in the row space of H */
+    MBBP_ENOMEM = -3,          /* host or device allocation failed */
+    MBBP_EDEVICE = -4,         /* a HIP call failed (message names it) */
+    MBBP_EUNSUPPORTED = -5,    /* beyond the implementation's limits (listed below) */
+    MBBP_EABORTED = -6         /* a persistent launch saw the abort flag */
+} mbbp_status;
+
+typedef enum { MBBP_FLOODING = 0, MBBP_LAYERED = 1 } mbbp_schedule;  /* Section II-B */
+typedef enum { MBBP_NMS = 0, MBBP_SPA = 1 } mbbp_rule;              /* eq. (1) / tanh rule */
+typedef enum { MBBP_MIN_WEIGHT = 0, MBBP_FWS = 1 } mbbp_select_rule; /* Section III-B */
+typedef enum { MBBP_PART_X = 0, MBBP_PART_Z = 1 } mbbp_part;
+
+/* Host CSR of a 0/1 matrix: row r has columns col_idx[row_ptr[r] .. row_ptr[r+1]),
+ * 0-based, strictly ascending. */
+typedef struct {
+    int32_t rows, cols;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+} mbbp_sparse;
+
+/* The L representations of one matrix H (eq. (3)): representation l is H with
+ * the rows rows[basis_ptr[l] .. basis_ptr[l+1]) appended in that order.  An
+ * entry r >= 0 duplicates row r of H; an entry r < 0 appends row (-r - 1) of
+ * `extra`, which must lie in the row space of H (checked by GF(2) elimination;
+ * its syndrome bit is then the matching sum of syndrome bits). */
+typedef struct {
+    int32_t L;
+    const int32_t *basis_ptr;  /* [L + 1], basis_ptr[0] = 0, non-decreasing */
+    const int32_t *rows;       /* [basis_ptr[L]] */
+    const mbbp_sparse *extra;  /* may be NULL when no entry is negative */
+} mbbp_basis_list;
+
+typedef struct {
+    mbbp_basis_list hx;  /* representations of H_X (used by part Z) */
+    mbbp_basis_list hz;  /* representations of H_Z (used by part X) */
+} mbbp_bases;
+
+#define MBBP_FLAG_FIXED_T 1u  /* diagnostic: run exactly T iterations, no early stop */
+
+typedef struct {
+    int32_t rule;        /* mbbp_rule, default MBBP_NMS */
+    float alpha;         /* normalisation of eq. (1), default 0.875 (Section IV); unused by SPA */
+    float r_max;         /* check messages are clamped to [-r_max, r_max], default 65536 */
+    int32_t select;      /* mbbp_select_rule, default MBBP_MIN_WEIGHT */
+    int64_t max_batch;   /* largest `shots` of any later call (sizes the workspace), default 1<<20 */
+    uint32_t flags;      /* MBBP_FLAG_* */
+} mbbp_params;
+
+/* Fill *p with the defaults above. */
+mbbp_status mbbp_params_default(mbbp_params *p);
+
+/* Build a decoder (host preprocessing + device upload, synchronous).
+ * H_X (m_X x n) and H_Z (m_Z x n) must satisfy H_X H_Z^T = 0 (Section II-A).
+ * T >= 0 is the iteration cap (I_max of Section IV), schedule an mbbp_schedule.
+ * Everything is deep-copied; the caller may free its arrays on return.
+ * Limits (MBBP_EUNSUPPORTED): row weight of every representation in [2, 8]
+ * (weight < 2 is MBBP_EINVAL), column weight <= 8, 1 <= L <= 64, n <= 1024,
+ * T <= 32767.  Uses the current HIP device. */
+mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mbbp_bases *bases,
+                        int32_t T, int32_t schedule, const mbbp_params *params, mbbp_ctx **out);
+
+/* Release the decoder and its device memory (synchronises its work first). */
+void mbbp_destroy(mbbp_ctx *ctx);
+
+/* Decode `shots` syndrome pairs (Algorithm 1 for both parts).
+ * syn_x   device [shots][ceil(m_Z/64)]   s_X = H_Z e_X
+ * syn_z   device [shots][ceil(m_X/64)]   s_Z = H_X e_Z
+ * prior_x device float [n] (prior_per_shot = 0) or [shots][n]: LLR log((1-q)/q)
+ * prior_z likewise (Section II-B initialisation)
+ * corr_x, corr_z device [shots][ceil(n/64)]   chosen estimate (all-zero if none converged)
+ * conv_x, conv_z device uint64 [shots]  bit l set iff representation l converged
+ * basis_x, basis_z device int16 [shots] chosen representation, -1 if none converged
+ * 0 < shots <= max_batch.  Deterministic: identical inputs give identical bits. */
+mbbp_status mbbp_decode(mbbp_ctx *ctx, int64_t shots,
+                        const uint64_t *syn_x, const uint64_t *syn_z,
+                        const float *prior_x, const float *prior_z, int32_t prior_per_shot,
+                        uint64_t *corr_x, uint64_t *corr_z,
+                        uint64_t *conv_x, uint64_t *conv_z,
+                        int16_t *basis_x, int16_t *basis_z, void *hip_stream);
+
+/* One part, every representation's own result (for inspection and parity):
+ * cand  device [shots][L][ceil(n/64)]  hard decision of each representation at its stop
+ * kstat device uint16 [shots][L]       iterations used (low 15 bits), bit 15 = converged
+ * llr   device float [shots][L][n] or NULL: posteriors at the stop (after T with FIXED_T)
+ * Same syndrome/prior conventions as mbbp_decode. */
+mbbp_status mbbp_decode_detail(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn,
+                               const float *prior, int32_t prior_per_shot,
+                               uint64_t *cand, uint16_t *kstat, float *llr, void *hip_stream);
+
+/* Counter-based depolarizing noise (code-capacity: X, Y, Z each with probability
+ * p/3): qubit q of shot s uses the 32-bit half (q%2) of word (q%8)/2 of
+ * Philox4x64-10(counter = (s, q/8, 0, 0), key = (seed, 0)) [Salmon et al. SC'11];
+ * u < t1 -> X, u < t2 -> Y, u < t3 -> Z with t_k = floor(k * (p/3) * 2^32) in
+ * double precision.  Shots are indexed shot0 .. shot0 + shots - 1.
+ * err_x, err_z device [shots][ceil(n/64)]; syn_x = H_Z e_X, syn_z = H_X e_Z as above.
+ * 0 <= p <= 1, 0 < shots <= max_batch. */
+mbbp_status mbbp_sample(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
+                        uint64_t *err_x, uint64_t *err_z, uint64_t *syn_x, uint64_t *syn_z,
+                        void *hip_stream);
+
+/* Logical-failure test (Section II-A): fail[s] bit 0 = part X failed
+ * (residual e_X ^ corr_x not a stabilizer: H_Z r != 0 or L_Z r != 0), bit 1 = part Z.
+ * All pointers device memory, [shots][ceil(n/64)] and uint8 [shots]. */
+mbbp_status mbbp_failures(mbbp_ctx *ctx, int64_t shots, const uint64_t *err_x, const uint64_t *err_z,
+                          const uint64_t *corr_x, const uint64_t *corr_z, uint8_t *fail,
+                          void *hip_stream);
+
+/* The batched form of mbbp_decode: one persistent launch over a work queue of
+ * (part, representation, shot chunk) items of uneven size, with per-instance
+ * early exit and refill.  Outputs are bit-identical to mbbp_decode. */
+mbbp_status mbbp_decode_batched(mbbp_ctx *ctx, int64_t shots,
+                                const uint64_t *syn_x, const uint64_t *syn_z,
+                                const float *prior_x, const float *prior_z, int32_t prior_per_shot,
+                                uint64_t *corr_x, uint64_t *corr_z,
+                                uint64_t *conv_x, uint64_t *conv_z,
+                                int16_t *basis_x, int16_t *basis_z, void *hip_stream);
+
+/* Counter indices of mbbp_run. */
+enum {
+    MBBP_CNT_FAIL = 0,        /* shots with a logical failure in either part */
+    MBBP_CNT_FAIL_X = 1,
+    MBBP_CNT_FAIL_Z = 2,
+    MBBP_CNT_SUM_KMAX = 3,    /* sum over shots of max iterations over all 2L instances */
+    MBBP_CNT_SUM_K = 4,       /* sum over (shot, part, representation) of iterations */
+    MBBP_CNT_EDGE_UPDATES = 5,/* sum of iterations x edges of that representation */
+    MBBP_CNT_NOCONV = 6,      /* (shot, part) pairs where no representation converged */
+    MBBP_CNT_TIES = 7,        /* (shot, part) pairs whose least weight is shared by distinct candidates */
+    MBBP_NUM_COUNTERS = 8
+};
+
+/* The whole path for shots [shot0, shot0 + shots): noise (mbbp_sample), the
+ * batched decoder, the decision and the failure test, replayed from a HIP graph
+ * captured on first use for this `shots`.  counters: device int64
+ * [MBBP_NUM_COUNTERS], ACCUMULATED into (the caller zeroes it).  Uniform
+ * priors log((1 - 2p/3) / (2p/3)) for both parts. */
+mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
+                     int64_t *counters, void *hip_stream);
+
+/* Algorithm 2 on host memory: perm is a permutation of the m checks (root
+ * order); check_sets[m] receives the 1-based subtree of each check, order[m]
+ * the checks in acceptance order (subtree 1 first), *n_subtrees their number. */
+mbbp_status mbbp_subtrees(const mbbp_sparse *H, const int32_t *perm, int32_t *check_sets,
+                          int32_t *order, int32_t *n_subtrees);
+
+/* Representations from subtrees (host).  perms: [n_perms][m] root orders.
+ * mode 0: distinct maximal subtrees of perms[0], perms[1], ... in discovery
+ *         order, rows in acceptance order, until L are found (fewer: MBBP_EINVAL).
+ * mode 1: representation l appends the first round(l m / (L-1)) rows (halves
+ *         up) of perms[l]'s acceptance order (needs n_perms >= L): sizes ramp
+ *         from 0 to m.
+ * Output basis_ptr[L + 1] and rows[rows_cap] (H row indices). */
+mbbp_status mbbp_build_bases(const mbbp_sparse *H, int32_t mode, int32_t L, int32_t n_perms,
+                             const int32_t *perms, int32_t *basis_ptr, int32_t *rows,
+                             int32_t rows_cap);
+
+/* Logical operators (host copies): LX [k][ceil(n/64)] spans ker H_Z modulo the
+ * row space of H_X, LZ spans ker H_X modulo the row space of H_Z; *k = n -
+ * rank H_X - rank H_Z.  Either array may be NULL to query k. */
+mbbp_status mbbp_logicals(mbbp_ctx *ctx, uint64_t *LX, uint64_t *LZ, int32_t *k);
+
+/* Edges of each representation of a part (host int64 [L]). */
+mbbp_status mbbp_edge_counts(mbbp_ctx *ctx, int32_t part, int64_t *edges);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *mbbp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBBP_H */

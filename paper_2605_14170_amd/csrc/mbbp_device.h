@@ -1,0 +1,118 @@
+// Device-side data shared by the host preprocessing and the HIP kernels of the
+// MBBP-LD library (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mbbp {
+
+constexpr int kMaxRowWeight = 8;   // row slots per check in LDS (stride 8)
+constexpr int kMaxVarDegree = 8;   // edge slots per variable
+constexpr int kMaxL = 64;
+constexpr int kMaxN = 1024;
+
+// Tables of one part (one parity-check matrix and its L representations).
+// Check j of representation l owns LDS edge ids j*8 .. j*8 + w_j - 1.
+struct DevPart {
+    int m, n, L;
+    int W, Ws;          // 64-bit words of n bits / of m bits
+    int Mmax;           // max checks over representations
+    int uniform_dc;     // 6 if every row of every representation has weight 6, else 0
+    const int32_t *M;   // [L] checks of each representation
+    const int32_t *E;   // [L] edges of each representation
+    const uint16_t *voff;   // [L][n][8] edge ids of the variable in slot s, ascending check order
+    const uint16_t *vid;    // [L][n] variable id of slot s (slots sorted by degree, descending)
+    const uint8_t *vdeg;    // [L][n] degree of the variable in slot s
+    const uint8_t *cw;      // [L][Mmax] row weight of check j (0 beyond M_l)
+    const int32_t *csrc;    // [L][Mmax] syndrome source of check j: j < m -> j; duplicate -> H row;
+                            // explicit row -> -(c + 1), combination c in comb_ptr/comb_idx
+    const int32_t *comb_ptr;
+    const int32_t *comb_idx;
+    const int32_t *hrow_ptr;   // H in CSR (sampler / failure test)
+    const int32_t *hrow_idx;
+    const uint64_t *logical;   // [k][W] logical operators of the other type (failure test)
+    int k;
+};
+
+// One BP launch (plain or persistent).
+struct BPArgs {
+    DevPart part[2];
+    const DevPart *dparts;   // the same two parts in device memory (read by bp_kernel)
+    int part0, nparts;       // parts handled: part0 .. part0 + nparts - 1
+    int L;                   // representations per part (equal for both parts)
+    int T;
+    float alpha, rmax;
+    int fixed_T;
+    int64_t shots;
+    const uint64_t *syn[2];  // [shots][Ws]
+    const float *prior[2];   // [n] or [shots][n]
+    int prior_per_shot;
+    uint64_t *cand[2];       // [shots][L][W]
+    uint16_t *kstat[2];      // [shots][L]
+    float *llr[2];           // [shots][L][n] or null
+    // work items
+    int persistent;          // 0: item = global wave id, 1: atomic queue
+    int chunk;               // shots per item
+    int64_t n_items;
+    const int32_t *item_order;  // persistent: [n_items_per_shotrange] (part, l) pairs ordered heavy first
+    int n_pl;                // number of (part, l) pairs
+    int64_t n_chunks;        // chunks per (part, l)
+    unsigned long long *queue;
+    int inst_bytes;          // LDS bytes per instance
+    int msg_bytes;           // MSG part of an instance (floats * 4)
+};
+
+struct SampleArgs {
+    DevPart part[2];         // part[0] uses H_Z (syn_x), part[1] uses H_X (syn_z)
+    int n;
+    uint64_t seed;
+    uint64_t t1, t2, t3;
+    int64_t shot0, shots;
+    uint64_t *err[2];        // [shots][W]  e_X, e_Z
+    uint64_t *syn[2];        // [shots][Ws] s_X = H_Z e_X, s_Z = H_X e_Z
+    const int64_t *desc;     // optional device (seed, shot0) override for graph replay, or null
+};
+
+struct SelectArgs {
+    DevPart part[2];
+    int part0, nparts;
+    int rule;                // 0 least weight, 1 FWS
+    int64_t shots;
+    const uint64_t *cand[2];
+    const uint16_t *kstat[2];
+    uint64_t *corr[2];
+    uint64_t *conv[2];
+    int16_t *basis[2];
+    int64_t *counters;       // optional: SUM_KMAX, SUM_K, EDGE_UPDATES, NOCONV, TIES
+    int *kmax_shot;          // optional [shots] scratch for the per-shot max over both parts
+};
+
+struct FailArgs {
+    DevPart part[2];
+    int64_t shots;
+    const uint64_t *err[2];
+    const uint64_t *corr[2];
+    uint8_t *fail;           // optional [shots]
+    int64_t *counters;       // optional FAIL, FAIL_X, FAIL_Z, SUM_KMAX
+    const int *kmax_shot;    // optional
+};
+
+// Launchers (mbbp_kernels*.hip).  Return hipError_t of the launch.
+struct BPConfig {
+    int lpi;        // lanes per instance: 16, 32 or 64
+    int waves_per_block;
+    int chunk;      // persistent: shots per work item
+    int blocks;     // persistent: grid size
+};
+
+hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s);
+hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
+hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_fail(const FailArgs &a, hipStream_t s);
+hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncounters, hipStream_t s);
+int bp_max_passes(int lpi);  // register slots available per lane for this lpi
+bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
+size_t bp_lds_limit();
+
+}  // namespace mbbp

@@ -1,0 +1,868 @@
+// Host side of the MBBP-LD library: argument validation, GF(2) algebra, maximal
+// subtrees (Algorithm 2), representation assembly, packing of the per-representation
+// tables consumed by the kernels, device memory, and the C ABI of include/mbbp.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mbbp.h"
+#include "mbbp_device.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mbbp_status fail(mbbp_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define MBBP_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(MBBP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+using Row = std::vector<int32_t>;  // sorted column indices
+
+// ----------------------------------------------------------------------------- GF(2)
+
+struct BitMat {
+    int cols = 0, words = 0;
+    std::vector<uint64_t> data;  // rows x words
+    int rows() const { return words ? (int)(data.size() / words) : 0; }
+    uint64_t *row(int r) { return data.data() + (size_t)r * words; }
+    const uint64_t *row(int r) const { return data.data() + (size_t)r * words; }
+};
+
+inline bool bit(const uint64_t *v, int i) { return (v[i >> 6] >> (i & 63)) & 1u; }
+
+// Reduced row-echelon basis of a row space, with, for each reduced row, the set of
+// original rows it is the sum of (so membership also yields the combination).
+struct RowSpace {
+    int n = 0, m = 0, wn = 0, wm = 0;
+    std::vector<std::vector<uint64_t>> red, comb;
+    std::vector<int> pivot;
+
+    void build(const std::vector<Row> &rows, int ncols) {
+        n = ncols;
+        m = (int)rows.size();
+        wn = (n + 63) / 64;
+        wm = std::max(1, (m + 63) / 64);
+        red.clear(); comb.clear(); pivot.clear();
+        for (int j = 0; j < m; ++j) {
+            std::vector<uint64_t> v(wn, 0), c(wm, 0);
+            for (int col : rows[j]) v[col >> 6] ^= 1ull << (col & 63);
+            c[j >> 6] |= 1ull << (j & 63);
+            insert(v, c);
+        }
+    }
+    // Reduce v (and its combination c) by the basis; returns true iff v becomes 0.
+    bool reduce(std::vector<uint64_t> &v, std::vector<uint64_t> *c) const {
+        for (size_t r = 0; r < red.size(); ++r) {
+            if (bit(v.data(), pivot[r])) {
+                for (int w = 0; w < wn; ++w) v[w] ^= red[r][w];
+                if (c)
+                    for (int w = 0; w < wm; ++w) (*c)[w] ^= comb[r][w];
+            }
+        }
+        for (uint64_t x : v)
+            if (x) return false;
+        return true;
+    }
+    // Insert a vector (no-op if dependent).  Keeps every stored row reduced
+    // against the pivots of the others.
+    bool insert(std::vector<uint64_t> v, std::vector<uint64_t> c) {
+        if (reduce(v, &c)) return false;
+        int p = -1;
+        for (int w = 0; w < wn && p < 0; ++w)
+            if (v[w]) p = w * 64 + __builtin_ctzll(v[w]);
+        for (size_t r = 0; r < red.size(); ++r) {
+            if (bit(red[r].data(), p)) {
+                for (int w = 0; w < wn; ++w) red[r][w] ^= v[w];
+                for (int w = 0; w < wm; ++w) comb[r][w] ^= c[w];
+            }
+        }
+        red.push_back(std::move(v));
+        comb.push_back(std::move(c));
+        pivot.push_back(p);
+        return true;
+    }
+    int rank() const { return (int)red.size(); }
+};
+
+// Basis of the kernel {x : A x = 0} of A (rows as column lists), as bit vectors.
+std::vector<std::vector<uint64_t>> kernel_basis(const std::vector<Row> &A, int n) {
+    RowSpace rs;
+    rs.build(A, n);
+    const int wn = (n + 63) / 64;
+    std::vector<char> is_pivot(n, 0);
+    for (int p : rs.pivot) is_pivot[p] = 1;
+    std::vector<std::vector<uint64_t>> out;
+    for (int f = 0; f < n; ++f) {
+        if (is_pivot[f]) continue;
+        // x_f = 1, other free = 0; pivot variables from the reduced rows
+        std::vector<uint64_t> x(wn, 0);
+        x[f >> 6] |= 1ull << (f & 63);
+        for (size_t r = 0; r < rs.red.size(); ++r)
+            if (bit(rs.red[r].data(), f)) x[rs.pivot[r] >> 6] |= 1ull << (rs.pivot[r] & 63);
+        out.push_back(std::move(x));
+    }
+    return out;
+}
+
+// Logical operators: a basis of ker(A) modulo the row space of B (A B^T = 0).
+std::vector<std::vector<uint64_t>> logicals(const std::vector<Row> &A, const std::vector<Row> &B, int n) {
+    RowSpace rs;
+    rs.build(B, n);
+    std::vector<std::vector<uint64_t>> out;
+    const int wm = rs.wm;
+    for (auto &v : kernel_basis(A, n)) {
+        std::vector<uint64_t> c(wm, 0);
+        std::vector<uint64_t> t = v;
+        if (!rs.reduce(t, nullptr)) {
+            out.push_back(v);
+            rs.insert(v, c);
+        }
+    }
+    return out;
+}
+
+// ----------------------------------------------------------------------------- validation
+
+mbbp_status read_sparse(const mbbp_sparse *H, const char *name, std::vector<Row> &rows) {
+    if (!H || !H->row_ptr || (!H->col_idx && H->rows > 0 && H->row_ptr[H->rows] > 0))
+        return fail(MBBP_EINVAL, std::string(name) + ": null matrix pointer");
+    if (H->rows <= 0 || H->cols <= 0) return fail(MBBP_EINVAL, std::string(name) + ": empty matrix");
+    if (H->row_ptr[0] != 0) return fail(MBBP_EINVAL, std::string(name) + ": row_ptr[0] != 0");
+    rows.assign(H->rows, Row());
+    for (int r = 0; r < H->rows; ++r) {
+        const int a = H->row_ptr[r], b = H->row_ptr[r + 1];
+        if (b < a) return fail(MBBP_EINVAL, std::string(name) + ": row_ptr not non-decreasing");
+        for (int k = a; k < b; ++k) {
+            const int c = H->col_idx[k];
+            if (c < 0 || c >= H->cols) return fail(MBBP_EINVAL, std::string(name) + ": column out of range");
+            if (k > a && c <= H->col_idx[k - 1])
+                return fail(MBBP_EINVAL, std::string(name) + ": columns not strictly ascending");
+            rows[r].push_back(c);
+        }
+    }
+    return MBBP_OK;
+}
+
+// ----------------------------------------------------------------------------- Algorithm 2
+
+// Maximal cycle-free subtrees.  Roots in the order of perm; a subtree grows
+// breadth-first (FIFO, neighbours in ascending index): a dequeued check with at
+// most one already-visited variable joins the current subtree, marks its variables
+// visited and queues their untested unassigned checks.  Variables and test marks
+// are reset for every root.
+mbbp_status subtrees(const std::vector<Row> &H, int n, const int32_t *perm, std::vector<int32_t> &cs,
+                     std::vector<int32_t> &order, int &nsub) {
+    const int m = (int)H.size();
+    std::vector<std::vector<int32_t>> vchk(n);
+    for (int j = 0; j < m; ++j)
+        for (int v : H[j]) vchk[v].push_back(j);
+    std::vector<char> seen(m, 0);
+    for (int i = 0; i < m; ++i) {
+        if (perm[i] < 0 || perm[i] >= m || seen[perm[i]])
+            return fail(MBBP_EINVAL, "perm is not a permutation of the checks");
+        seen[perm[i]] = 1;
+    }
+    cs.assign(m, 0);
+    order.clear();
+    nsub = 0;
+    std::vector<char> visited(n), tested(m);
+    std::vector<int32_t> queue;
+    for (int i = 0; i < m; ++i) {
+        const int root = perm[i];
+        if (cs[root]) continue;
+        ++nsub;
+        std::fill(visited.begin(), visited.end(), 0);
+        std::fill(tested.begin(), tested.end(), 0);
+        queue.assign(1, root);
+        for (size_t head = 0; head < queue.size(); ++head) {
+            const int u = queue[head];
+            tested[u] = 1;
+            int eta = 0;
+            for (int v : H[u]) eta += visited[v];
+            if (eta > 1 || cs[u]) continue;
+            cs[u] = nsub;
+            order.push_back(u);
+            for (int v : H[u]) {
+                visited[v] = 1;
+                for (int c : vchk[v])
+                    if (!tested[c] && !cs[c]) queue.push_back(c);
+            }
+        }
+    }
+    return MBBP_OK;
+}
+
+// ----------------------------------------------------------------------------- parts
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+struct HostPart {
+    int m = 0, n = 0, L = 0, Mmax = 0, uniform_dc = 0;
+    std::vector<Row> H;
+    std::vector<int32_t> M, E;
+    std::vector<uint16_t> voff, vid;
+    std::vector<uint8_t> vdeg, cw;
+    std::vector<int32_t> csrc, comb_ptr{0}, comb_idx;
+    std::vector<uint64_t> logical;
+    int k = 0;
+};
+
+mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &bl, const char *name,
+                       HostPart &P) {
+    const int m = (int)H.size();
+    P.m = m; P.n = n; P.H = H;
+    if (bl.L < 1) return fail(MBBP_EINVAL, std::string(name) + ": L < 1");
+    if (bl.L > mbbp::kMaxL) return fail(MBBP_EUNSUPPORTED, std::string(name) + ": L > 64");
+    if (!bl.basis_ptr) return fail(MBBP_EINVAL, std::string(name) + ": null basis_ptr");
+    if (bl.basis_ptr[0] != 0) return fail(MBBP_EINVAL, std::string(name) + ": basis_ptr[0] != 0");
+    for (int l = 0; l < bl.L; ++l)
+        if (bl.basis_ptr[l + 1] < bl.basis_ptr[l])
+            return fail(MBBP_EINVAL, std::string(name) + ": basis_ptr decreasing");
+    if (bl.basis_ptr[bl.L] > 0 && !bl.rows) return fail(MBBP_EINVAL, std::string(name) + ": null rows");
+    std::vector<Row> extra;
+    if (bl.extra) {
+        mbbp_status st = read_sparse(bl.extra, name, extra);
+        if (st != MBBP_OK) return st;
+        if (bl.extra->cols != n) return fail(MBBP_EINVAL, std::string(name) + ": extra rows have wrong width");
+    }
+    for (int j = 0; j < m; ++j) {
+        if ((int)H[j].size() < 2) return fail(MBBP_EINVAL, std::string(name) + ": row weight < 2");
+    }
+    RowSpace rs;
+    bool rs_built = false;
+    P.L = bl.L;
+    P.M.resize(bl.L);
+    P.E.resize(bl.L);
+    std::vector<std::vector<Row>> reps(bl.L);
+    std::vector<std::vector<int32_t>> srcs(bl.L);
+    for (int l = 0; l < bl.L; ++l) {
+        reps[l] = H;
+        srcs[l].resize(m);
+        for (int j = 0; j < m; ++j) srcs[l][j] = j;
+        for (int t = bl.basis_ptr[l]; t < bl.basis_ptr[l + 1]; ++t) {
+            const int r = bl.rows[t];
+            if (r >= 0) {
+                if (r >= m) return fail(MBBP_EINVAL, std::string(name) + ": basis row out of range");
+                reps[l].push_back(H[r]);
+                srcs[l].push_back(r);
+            } else {
+                const int e = -r - 1;
+                if (e >= (int)extra.size()) return fail(MBBP_EINVAL, std::string(name) + ": extra row out of range");
+                if ((int)extra[e].size() < 2) return fail(MBBP_EINVAL, std::string(name) + ": row weight < 2");
+                if (!rs_built) { rs.build(H, n); rs_built = true; }
+                std::vector<uint64_t> v(rs.wn, 0), c(rs.wm, 0);
+                for (int col : extra[e]) v[col >> 6] ^= 1ull << (col & 63);
+                if (!rs.reduce(v, &c))
+                    return fail(MBBP_ENOTINROWSPACE, std::string(name) + ": appended row not in the row space of H");
+                const int cix = (int)P.comb_ptr.size() - 1;
+                for (int j = 0; j < m; ++j)
+                    if (bit(c.data(), j)) P.comb_idx.push_back(j);
+                P.comb_ptr.push_back((int32_t)P.comb_idx.size());
+                reps[l].push_back(extra[e]);
+                srcs[l].push_back(-(cix + 1));
+            }
+        }
+        P.M[l] = (int)reps[l].size();
+        P.Mmax = std::max(P.Mmax, P.M[l]);
+    }
+    if ((int64_t)(P.Mmax + 1) * 8 > 65535)
+        return fail(MBBP_EUNSUPPORTED, std::string(name) + ": too many checks in a representation");
+    bool all6 = true;
+    for (int l = 0; l < bl.L; ++l)
+        for (auto &r : reps[l]) {
+            if ((int)r.size() > mbbp::kMaxRowWeight)
+                return fail(MBBP_EUNSUPPORTED, std::string(name) + ": row weight > 8");
+            all6 = all6 && r.size() == 6;
+        }
+    P.uniform_dc = all6 ? 6 : 0;
+    const int L = bl.L, Mmax = P.Mmax;
+    P.voff.assign((size_t)L * n * 8, 0);
+    P.vid.assign((size_t)L * n, 0);
+    P.vdeg.assign((size_t)L * n, 0);
+    P.cw.assign((size_t)L * Mmax, 0);
+    P.csrc.assign((size_t)L * Mmax, 0);
+    for (int l = 0; l < L; ++l) {
+        std::vector<std::vector<uint16_t>> vedges(n);
+        int E = 0;
+        for (int j = 0; j < P.M[l]; ++j) {
+            const Row &r = reps[l][j];
+            P.cw[(size_t)l * Mmax + j] = (uint8_t)r.size();
+            P.csrc[(size_t)l * Mmax + j] = srcs[l][j];
+            for (size_t k = 0; k < r.size(); ++k) vedges[r[k]].push_back((uint16_t)(j * 8 + k));
+            E += (int)r.size();
+        }
+        P.E[l] = E;
+        std::vector<int> slot(n);
+        for (int i = 0; i < n; ++i) slot[i] = i;
+        std::stable_sort(slot.begin(), slot.end(),
+                         [&](int a, int b) { return vedges[a].size() > vedges[b].size(); });
+        for (int s = 0; s < n; ++s) {
+            const int i = slot[s];
+            if ((int)vedges[i].size() > mbbp::kMaxVarDegree)
+                return fail(MBBP_EUNSUPPORTED, std::string(name) + ": column weight > 8");
+            P.vid[(size_t)l * n + s] = (uint16_t)i;
+            P.vdeg[(size_t)l * n + s] = (uint8_t)vedges[i].size();
+            for (int k = 0; k < 8; ++k)  // absent edges point at the sink row
+                P.voff[((size_t)l * n + s) * 8 + k] =
+                    k < (int)vedges[i].size() ? vedges[i][k] : (uint16_t)(Mmax * 8);
+        }
+    }
+    return MBBP_OK;
+}
+
+template <typename T>
+mbbp_status upload(DevBuf &b, const std::vector<T> &v) {
+    const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    MBBP_HIP(hipMalloc(&b.p, bytes));
+    if (!v.empty()) MBBP_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return MBBP_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- context
+
+struct RunGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t prep = nullptr;
+};
+
+struct mbbp_ctx {
+    int device = 0;
+    int n = 0, T = 0, schedule = 0;
+    mbbp_params params{};
+    HostPart hp[2];  // [0] = part X (H_Z), [1] = part Z (H_X)
+    std::vector<Row> HX, HZ;
+    std::vector<std::vector<uint64_t>> LX, LZ;
+    std::vector<std::unique_ptr<DevBuf>> bufs;
+    mbbp::DevPart dp[2]{};
+    const mbbp::DevPart *dparts = nullptr;  // dp[] copied to device memory
+    // workspace
+    uint64_t *cand[2]{};
+    uint16_t *kstat[2]{};
+    uint64_t *w_err[2]{}, *w_syn[2]{}, *w_corr[2]{}, *w_conv[2]{};
+    int16_t *w_basis[2]{};
+    float *w_prior[2]{};
+    int *w_kmax = nullptr;
+    int64_t *w_counters = nullptr;
+    int64_t *w_desc = nullptr;
+    unsigned long long *w_queue = nullptr;
+    int32_t *item_order = nullptr;
+    int cu_count = 256;
+    mbbp::BPConfig plain_cfg{16, 4, 0, 0};
+    mbbp::BPConfig batched_cfg{16, 4, 8, 0};
+    hipStream_t capture_stream = nullptr;
+    std::map<int64_t, RunGraph> graphs;
+
+    template <typename T>
+    mbbp_status alloc(T *&p, size_t count) {
+        auto b = std::make_unique<DevBuf>();
+        hipError_t e = hipMalloc(&b->p, std::max<size_t>(count * sizeof(T), 16));
+        if (e != hipSuccess) return fail(MBBP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        p = static_cast<T *>(b->p);
+        bufs.push_back(std::move(b));
+        return MBBP_OK;
+    }
+    template <typename T>
+    mbbp_status put(const T *&p, const std::vector<T> &v) {
+        auto b = std::make_unique<DevBuf>();
+        mbbp_status st = upload(*b, v);
+        if (st != MBBP_OK) return st;
+        p = static_cast<const T *>(b->p);
+        bufs.push_back(std::move(b));
+        return MBBP_OK;
+    }
+};
+
+namespace {
+
+mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint64_t>> &logi) {
+    HostPart &P = c->hp[pi];
+    mbbp::DevPart &D = c->dp[pi];
+    D.m = P.m; D.n = P.n; D.L = P.L;
+    D.W = (P.n + 63) / 64;
+    D.Ws = (P.m + 63) / 64;
+    D.Mmax = P.Mmax;
+    D.uniform_dc = P.uniform_dc;
+    mbbp_status st;
+    if ((st = c->put(D.M, P.M)) != MBBP_OK) return st;
+    if ((st = c->put(D.E, P.E)) != MBBP_OK) return st;
+    if ((st = c->put(D.voff, P.voff)) != MBBP_OK) return st;
+    if ((st = c->put(D.vid, P.vid)) != MBBP_OK) return st;
+    if ((st = c->put(D.vdeg, P.vdeg)) != MBBP_OK) return st;
+    if ((st = c->put(D.cw, P.cw)) != MBBP_OK) return st;
+    if ((st = c->put(D.csrc, P.csrc)) != MBBP_OK) return st;
+    if ((st = c->put(D.comb_ptr, P.comb_ptr)) != MBBP_OK) return st;
+    std::vector<int32_t> ci = P.comb_idx;
+    if ((st = c->put(D.comb_idx, ci)) != MBBP_OK) return st;
+    std::vector<int32_t> hp{0}, hi;
+    for (auto &r : P.H) {
+        hi.insert(hi.end(), r.begin(), r.end());
+        hp.push_back((int32_t)hi.size());
+    }
+    if ((st = c->put(D.hrow_ptr, hp)) != MBBP_OK) return st;
+    if ((st = c->put(D.hrow_idx, hi)) != MBBP_OK) return st;
+    std::vector<uint64_t> lg;
+    for (auto &v : logi) lg.insert(lg.end(), v.begin(), v.end());
+    P.logical = lg;
+    P.k = (int)logi.size();
+    D.k = P.k;
+    if ((st = c->put(D.logical, lg)) != MBBP_OK) return st;
+    return MBBP_OK;
+}
+
+int inst_bytes_for(const mbbp_ctx *c, int part0, int nparts, int *msg_bytes) {
+    int Mmax = 0, W = 0;
+    for (int p = part0; p < part0 + nparts; ++p) {
+        Mmax = std::max(Mmax, c->dp[p].Mmax);
+        W = std::max(W, c->dp[p].W);
+    }
+    // (Mmax + 1) rows: the last is the sink row of absent edges
+    *msg_bytes = (Mmax + 1) * 32;
+    const int bytes = (Mmax + 1) * 32 + (Mmax + 1) * 8 + W * 8;
+    return (bytes + 15) & ~15;
+}
+
+mbbp_status check_stream_ptrs(const void *p, const char *what) {
+    if (!p) return fail(MBBP_EINVAL, std::string("null pointer: ") + what);
+    return MBBP_OK;
+}
+
+mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint64_t *const syn[2],
+                   const float *const prior[2], int pps, uint64_t *const cand[2], uint16_t *const kstat[2],
+                   float *const llr[2], bool persistent, hipStream_t s) {
+    mbbp::BPArgs a{};
+    a.part[0] = c->dp[0];
+    a.part[1] = c->dp[1];
+    a.dparts = c->dparts;
+    a.part0 = part0;
+    a.nparts = nparts;
+    a.L = c->dp[0].L;
+    a.T = c->T;
+    a.alpha = c->params.alpha;
+    a.rmax = c->params.r_max;
+    a.fixed_T = (c->params.flags & MBBP_FLAG_FIXED_T) ? 1 : 0;
+    a.shots = shots;
+    a.prior_per_shot = pps;
+    for (int p = 0; p < 2; ++p) {
+        a.syn[p] = syn[p];
+        a.prior[p] = prior[p];
+        a.cand[p] = cand[p];
+        a.kstat[p] = kstat[p];
+        a.llr[p] = llr[p];
+    }
+    const mbbp::BPConfig cfg = persistent ? c->batched_cfg : c->plain_cfg;
+    const int G = 64 / cfg.lpi;
+    a.persistent = persistent ? 1 : 0;
+    a.chunk = persistent ? cfg.chunk : G;
+    a.n_chunks = (shots + a.chunk - 1) / a.chunk;
+    a.n_pl = nparts * c->dp[part0].L;
+    a.n_items = a.n_chunks * a.n_pl;
+    a.item_order = persistent ? c->item_order + (part0 == 1 ? 0 : 0) : nullptr;
+    if (persistent && nparts != 2) a.item_order = nullptr;
+    a.queue = c->w_queue;
+    a.inst_bytes = inst_bytes_for(c, part0, nparts, &a.msg_bytes);
+    mbbp::BPConfig run = cfg;
+    if (persistent) {
+        run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
+        hipError_t e = mbbp::launch_reset(c->w_queue, nullptr, 0, s);
+        if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("reset launch: ") + hipGetErrorString(e));
+    }
+    while (run.waves_per_block > 1 && (size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
+        run.waves_per_block /= 2;
+    if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
+        return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
+    hipError_t e = mbbp::launch_bp(a, run, c->schedule, c->params.rule, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("bp launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+mbbp_status run_select(mbbp_ctx *c, int part0, int nparts, int64_t shots, uint64_t *const corr[2],
+                       uint64_t *const conv[2], int16_t *const basis[2], int64_t *counters, int *kmax,
+                       hipStream_t s) {
+    mbbp::SelectArgs a{};
+    a.part[0] = c->dp[0];
+    a.part[1] = c->dp[1];
+    a.part0 = part0;
+    a.nparts = nparts;
+    a.rule = c->params.select;
+    a.shots = shots;
+    for (int p = 0; p < 2; ++p) {
+        a.cand[p] = c->cand[p];
+        a.kstat[p] = c->kstat[p];
+        a.corr[p] = corr[p];
+        a.conv[p] = conv[p];
+        a.basis[p] = basis[p];
+    }
+    a.counters = counters;
+    a.kmax_shot = kmax;
+    hipError_t e = mbbp::launch_select(a, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("select launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- C ABI
+
+extern "C" {
+
+const char *mbbp_last_error(void) { return g_last_error.c_str(); }
+
+mbbp_status mbbp_params_default(mbbp_params *p) {
+    if (!p) return fail(MBBP_EINVAL, "null params");
+    p->rule = MBBP_NMS;
+    p->alpha = 0.875f;
+    p->r_max = 65536.0f;
+    p->select = MBBP_MIN_WEIGHT;
+    p->max_batch = 1 << 20;
+    p->flags = 0;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_subtrees(const mbbp_sparse *H, const int32_t *perm, int32_t *check_sets, int32_t *order,
+                          int32_t *n_subtrees) {
+    std::vector<Row> rows;
+    mbbp_status st = read_sparse(H, "H", rows);
+    if (st != MBBP_OK) return st;
+    if (!perm || !check_sets || !order || !n_subtrees) return fail(MBBP_EINVAL, "null output pointer");
+    std::vector<int32_t> cs, ord;
+    int ns = 0;
+    try {
+        st = subtrees(rows, H->cols, perm, cs, ord, ns);
+    } catch (const std::bad_alloc &) {
+        return fail(MBBP_ENOMEM, "out of host memory");
+    }
+    if (st != MBBP_OK) return st;
+    std::copy(cs.begin(), cs.end(), check_sets);
+    std::copy(ord.begin(), ord.end(), order);
+    *n_subtrees = ns;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_build_bases(const mbbp_sparse *H, int32_t mode, int32_t L, int32_t n_perms, const int32_t *perms,
+                             int32_t *basis_ptr, int32_t *rows_out, int32_t rows_cap) {
+    std::vector<Row> rows;
+    mbbp_status st = read_sparse(H, "H", rows);
+    if (st != MBBP_OK) return st;
+    if (L < 1 || n_perms < 1 || !perms || !basis_ptr || (!rows_out && rows_cap > 0) || rows_cap < 0)
+        return fail(MBBP_EINVAL, "bad arguments to mbbp_build_bases");
+    const int m = H->rows;
+    std::vector<std::vector<int32_t>> reps;
+    try {
+        if (mode == 0) {
+            std::vector<std::vector<int32_t>> seen_sets;
+            for (int k = 0; k < n_perms && (int)reps.size() < L; ++k) {
+                std::vector<int32_t> cs, ord;
+                int ns = 0;
+                st = subtrees(rows, H->cols, perms + (size_t)k * m, cs, ord, ns);
+                if (st != MBBP_OK) return st;
+                size_t pos = 0;
+                for (int s = 1; s <= ns && (int)reps.size() < L; ++s) {
+                    std::vector<int32_t> t;
+                    while (pos < ord.size() && cs[ord[pos]] == s) t.push_back(ord[pos++]);
+                    std::vector<int32_t> key = t;
+                    std::sort(key.begin(), key.end());
+                    if (std::find(seen_sets.begin(), seen_sets.end(), key) != seen_sets.end()) continue;
+                    seen_sets.push_back(key);
+                    reps.push_back(t);
+                }
+            }
+            if ((int)reps.size() < L) return fail(MBBP_EINVAL, "not enough distinct subtrees for L");
+        } else if (mode == 1) {
+            if (n_perms < L) return fail(MBBP_EINVAL, "ramp mode needs n_perms >= L");
+            for (int l = 0; l < L; ++l) {
+                std::vector<int32_t> cs, ord;
+                int ns = 0;
+                st = subtrees(rows, H->cols, perms + (size_t)l * m, cs, ord, ns);
+                if (st != MBBP_OK) return st;
+                const int r = L == 1 ? 0 : (int)((2LL * l * m + (L - 1)) / (2LL * (L - 1)));
+                reps.emplace_back(ord.begin(), ord.begin() + r);
+            }
+        } else {
+            return fail(MBBP_EINVAL, "unknown basis mode");
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(MBBP_ENOMEM, "out of host memory");
+    }
+    int64_t total = 0;
+    for (auto &r : reps) total += (int64_t)r.size();
+    if (total > rows_cap) return fail(MBBP_EINVAL, "rows_cap too small");
+    basis_ptr[0] = 0;
+    int64_t used = 0;
+    for (int l = 0; l < L; ++l) {
+        for (int32_t r : reps[l]) rows_out[used++] = r;
+        basis_ptr[l + 1] = (int32_t)used;
+    }
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mbbp_bases *bases, int32_t T,
+                        int32_t schedule, const mbbp_params *params, mbbp_ctx **out) {
+    if (!out) return fail(MBBP_EINVAL, "null out");
+    *out = nullptr;
+    if (!bases) return fail(MBBP_EINVAL, "null bases");
+    if (T < 0) return fail(MBBP_EINVAL, "T < 0");
+    if (T > 32767) return fail(MBBP_EUNSUPPORTED, "T > 32767");
+    if (schedule != MBBP_FLOODING && schedule != MBBP_LAYERED) return fail(MBBP_EINVAL, "unknown schedule");
+    mbbp_params prm;
+    mbbp_params_default(&prm);
+    if (params) prm = *params;
+    if (prm.rule != MBBP_NMS && prm.rule != MBBP_SPA) return fail(MBBP_EINVAL, "unknown rule");
+    if (prm.select != MBBP_MIN_WEIGHT && prm.select != MBBP_FWS) return fail(MBBP_EINVAL, "unknown select rule");
+    if (!(prm.alpha > 0.0f) || !(prm.r_max > 0.0f) || !std::isfinite(prm.alpha) || !std::isfinite(prm.r_max))
+        return fail(MBBP_EINVAL, "alpha and r_max must be positive and finite");
+    if (prm.max_batch < 1) return fail(MBBP_EINVAL, "max_batch < 1");
+    std::unique_ptr<mbbp_ctx> c;
+    try {
+        c.reset(new mbbp_ctx());
+        std::vector<Row> hx, hz;
+        mbbp_status st;
+        if ((st = read_sparse(H_X, "H_X", hx)) != MBBP_OK) return st;
+        if ((st = read_sparse(H_Z, "H_Z", hz)) != MBBP_OK) return st;
+        if (H_X->cols != H_Z->cols) return fail(MBBP_EINVAL, "H_X and H_Z have different n");
+        const int n = H_X->cols;
+        if (n > mbbp::kMaxN) return fail(MBBP_EUNSUPPORTED, "n > 1024");
+        // H_X H_Z^T = 0 (Section II-A)
+        {
+            std::vector<std::vector<uint64_t>> zb(hz.size(), std::vector<uint64_t>((n + 63) / 64, 0));
+            for (size_t j = 0; j < hz.size(); ++j)
+                for (int col : hz[j]) zb[j][col >> 6] |= 1ull << (col & 63);
+            for (auto &rx : hx)
+                for (auto &z : zb) {
+                    int par = 0;
+                    for (int col : rx) par ^= (int)((z[col >> 6] >> (col & 63)) & 1u);
+                    if (par) return fail(MBBP_EINVAL, "H_X H_Z^T != 0");
+                }
+        }
+        c->n = n;
+        c->T = T;
+        c->schedule = schedule;
+        c->params = prm;
+        c->HX = hx;
+        c->HZ = hz;
+        if ((st = build_part(hz, n, bases->hz, "bases.hz", c->hp[0])) != MBBP_OK) return st;
+        if ((st = build_part(hx, n, bases->hx, "bases.hx", c->hp[1])) != MBBP_OK) return st;
+        if (c->hp[0].L != c->hp[1].L) return fail(MBBP_EINVAL, "bases.hx and bases.hz have different L");
+        c->LZ = logicals(hx, hz, n);  // ker H_X mod rowspace H_Z
+        c->LX = logicals(hz, hx, n);  // ker H_Z mod rowspace H_X
+        MBBP_HIP(hipGetDevice(&c->device));
+        hipDeviceProp_t prop;
+        MBBP_HIP(hipGetDeviceProperties(&prop, c->device));
+        c->cu_count = prop.multiProcessorCount;
+        // part X (H_Z) tests residuals with H_Z and L_Z; part Z with H_X and L_X
+        if ((st = upload_part(c.get(), 0, c->LZ)) != MBBP_OK) return st;
+        if ((st = upload_part(c.get(), 1, c->LX)) != MBBP_OK) return st;
+        {
+            std::vector<mbbp::DevPart> both{c->dp[0], c->dp[1]};
+            if ((st = c->put(c->dparts, both)) != MBBP_OK) return st;
+        }
+        // schedule support
+        for (int lpi : {16, 32, 64}) {
+            (void)lpi;
+        }
+        if (schedule != MBBP_FLOODING) return fail(MBBP_EUNSUPPORTED, "schedule not built yet");
+        // pick the plain configuration: widest instances that fit the register slots
+        int need16 = 0;
+        for (int p = 0; p < 2; ++p)
+            need16 = std::max({need16, (c->dp[p].n + 15) / 16, (c->dp[p].Mmax + 15) / 16});
+        int lpi = need16 <= 9 ? 16 : 0;
+        if (!lpi) {
+            int need32 = 0;
+            for (int p = 0; p < 2; ++p) need32 = std::max({need32, (c->dp[p].n + 31) / 32, (c->dp[p].Mmax + 31) / 32});
+            lpi = need32 <= 9 ? 32 : 64;
+        }
+        int need = 0;
+        for (int p = 0; p < 2; ++p)
+            need = std::max({need, (c->dp[p].n + lpi - 1) / lpi, (c->dp[p].Mmax + lpi - 1) / lpi});
+        if (!mbbp::bp_supported(lpi, need, c->dp[0].uniform_dc, prm.rule, schedule))
+            return fail(MBBP_EUNSUPPORTED, "code too large for the register tables");
+        c->plain_cfg = mbbp::BPConfig{lpi, 4, 0, 0};
+        c->batched_cfg = mbbp::BPConfig{lpi, 4, 8, c->cu_count * 4};
+        // workspace
+        const int64_t B = prm.max_batch;
+        for (int p = 0; p < 2; ++p) {
+            const int L = c->dp[p].L, W = c->dp[p].W, Ws = c->dp[p].Ws;
+            if ((st = c->alloc(c->cand[p], (size_t)B * L * W)) != MBBP_OK) return st;
+            if ((st = c->alloc(c->kstat[p], (size_t)B * L)) != MBBP_OK) return st;
+            (void)Ws;
+        }
+        if ((st = c->alloc(c->w_queue, 1)) != MBBP_OK) return st;
+        // heavy-first order of (part, representation) work for the persistent form
+        {
+            std::vector<std::pair<int64_t, int32_t>> w;
+            const int L = c->dp[0].L;
+            for (int p = 0; p < 2; ++p)
+                for (int l = 0; l < L; ++l) w.push_back({-(int64_t)c->hp[p].E[l], p * L + l});
+            std::stable_sort(w.begin(), w.end());
+            std::vector<int32_t> order;
+            for (auto &x : w) order.push_back(x.second);
+            const int32_t *d = nullptr;
+            if ((st = c->put(d, order)) != MBBP_OK) return st;
+            c->item_order = const_cast<int32_t *>(d);
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(MBBP_ENOMEM, "out of host memory");
+    }
+    *out = c.release();
+    return MBBP_OK;
+}
+
+void mbbp_destroy(mbbp_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+}
+
+mbbp_status mbbp_decode_detail(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn, const float *prior,
+                               int32_t prior_per_shot, uint64_t *cand, uint16_t *kstat, float *llr,
+                               void *hip_stream) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (part != 0 && part != 1) return fail(MBBP_EINVAL, "part must be 0 (X) or 1 (Z)");
+    if (shots < 1 || shots > ctx->params.max_batch) return fail(MBBP_EINVAL, "shots out of range");
+    mbbp_status st;
+    if ((st = check_stream_ptrs(syn, "syn")) != MBBP_OK) return st;
+    if ((st = check_stream_ptrs(prior, "prior")) != MBBP_OK) return st;
+    if ((st = check_stream_ptrs(cand, "cand")) != MBBP_OK) return st;
+    if ((st = check_stream_ptrs(kstat, "kstat")) != MBBP_OK) return st;
+    const uint64_t *sy[2] = {syn, syn};
+    const float *pr[2] = {prior, prior};
+    uint64_t *cd[2] = {cand, cand};
+    uint16_t *ks[2] = {kstat, kstat};
+    float *ll[2] = {llr, llr};
+    return run_bp(ctx, part, 1, shots, sy, pr, prior_per_shot ? 1 : 0, cd, ks, ll, false,
+                  static_cast<hipStream_t>(hip_stream));
+}
+
+static mbbp_status decode_common(mbbp_ctx *ctx, int64_t shots, const uint64_t *syn_x, const uint64_t *syn_z,
+                                 const float *prior_x, const float *prior_z, int32_t pps, uint64_t *corr_x,
+                                 uint64_t *corr_z, uint64_t *conv_x, uint64_t *conv_z, int16_t *basis_x,
+                                 int16_t *basis_z, void *hip_stream, bool persistent) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (shots < 1 || shots > ctx->params.max_batch) return fail(MBBP_EINVAL, "shots out of range");
+    const void *ptrs[] = {syn_x, syn_z, prior_x, prior_z, corr_x, corr_z, conv_x, conv_z, basis_x, basis_z};
+    for (const void *p : ptrs)
+        if (!p) return fail(MBBP_EINVAL, "null device pointer");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const uint64_t *sy[2] = {syn_x, syn_z};
+    const float *pr[2] = {prior_x, prior_z};
+    float *ll[2] = {nullptr, nullptr};
+    mbbp_status st = run_bp(ctx, 0, 2, shots, sy, pr, pps ? 1 : 0, ctx->cand, ctx->kstat, ll, persistent, s);
+    if (st != MBBP_OK) return st;
+    uint64_t *co[2] = {corr_x, corr_z};
+    uint64_t *cv[2] = {conv_x, conv_z};
+    int16_t *bs[2] = {basis_x, basis_z};
+    return run_select(ctx, 0, 2, shots, co, cv, bs, nullptr, nullptr, s);
+}
+
+mbbp_status mbbp_decode(mbbp_ctx *ctx, int64_t shots, const uint64_t *syn_x, const uint64_t *syn_z,
+                        const float *prior_x, const float *prior_z, int32_t prior_per_shot, uint64_t *corr_x,
+                        uint64_t *corr_z, uint64_t *conv_x, uint64_t *conv_z, int16_t *basis_x, int16_t *basis_z,
+                        void *hip_stream) {
+    return decode_common(ctx, shots, syn_x, syn_z, prior_x, prior_z, prior_per_shot, corr_x, corr_z, conv_x,
+                         conv_z, basis_x, basis_z, hip_stream, false);
+}
+
+mbbp_status mbbp_decode_batched(mbbp_ctx *ctx, int64_t shots, const uint64_t *syn_x, const uint64_t *syn_z,
+                                const float *prior_x, const float *prior_z, int32_t prior_per_shot,
+                                uint64_t *corr_x, uint64_t *corr_z, uint64_t *conv_x, uint64_t *conv_z,
+                                int16_t *basis_x, int16_t *basis_z, void *hip_stream) {
+    return decode_common(ctx, shots, syn_x, syn_z, prior_x, prior_z, prior_per_shot, corr_x, corr_z, conv_x,
+                         conv_z, basis_x, basis_z, hip_stream, true);
+}
+
+static void thresholds(double p, uint64_t t[3]) {
+    for (int k = 1; k <= 3; ++k) t[k - 1] = (uint64_t)std::floor((double)k * (p / 3.0) * 4294967296.0);
+}
+
+mbbp_status mbbp_sample(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, uint64_t *err_x,
+                        uint64_t *err_z, uint64_t *syn_x, uint64_t *syn_z, void *hip_stream) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (!(p >= 0.0 && p <= 1.0)) return fail(MBBP_EINVAL, "p outside [0, 1]");
+    if (shots < 1 || shots > ctx->params.max_batch || shot0 < 0) return fail(MBBP_EINVAL, "shots out of range");
+    if (!err_x || !err_z || !syn_x || !syn_z) return fail(MBBP_EINVAL, "null device pointer");
+    mbbp::SampleArgs a{};
+    a.part[0] = ctx->dp[0];
+    a.part[1] = ctx->dp[1];
+    a.n = ctx->n;
+    a.seed = seed;
+    uint64_t t[3];
+    thresholds(p, t);
+    a.t1 = t[0]; a.t2 = t[1]; a.t3 = t[2];
+    a.shot0 = shot0;
+    a.shots = shots;
+    a.err[0] = err_x; a.err[1] = err_z;
+    a.syn[0] = syn_x; a.syn[1] = syn_z;
+    a.desc = nullptr;
+    hipError_t e = mbbp::launch_sample(a, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("sample launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_failures(mbbp_ctx *ctx, int64_t shots, const uint64_t *err_x, const uint64_t *err_z,
+                          const uint64_t *corr_x, const uint64_t *corr_z, uint8_t *fail_out, void *hip_stream) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (shots < 1 || shots > ctx->params.max_batch) return fail(MBBP_EINVAL, "shots out of range");
+    if (!err_x || !err_z || !corr_x || !corr_z || !fail_out) return fail(MBBP_EINVAL, "null device pointer");
+    mbbp::FailArgs a{};
+    a.part[0] = ctx->dp[0];
+    a.part[1] = ctx->dp[1];
+    a.shots = shots;
+    a.err[0] = err_x; a.err[1] = err_z;
+    a.corr[0] = corr_x; a.corr[1] = corr_z;
+    a.fail = fail_out;
+    hipError_t e = mbbp::launch_fail(a, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("failure launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, int64_t *counters,
+                     void *hip_stream) {
+    (void)ctx; (void)seed; (void)p; (void)shot0; (void)shots; (void)counters; (void)hip_stream;
+    return fail(MBBP_EUNSUPPORTED, "mbbp_run not built yet");
+}
+
+mbbp_status mbbp_logicals(mbbp_ctx *ctx, uint64_t *LX, uint64_t *LZ, int32_t *k) {
+    if (!ctx || !k) return fail(MBBP_EINVAL, "null argument");
+    *k = (int32_t)ctx->LX.size();
+    const int W = (ctx->n + 63) / 64;
+    if (LX)
+        for (size_t r = 0; r < ctx->LX.size(); ++r) std::memcpy(LX + r * W, ctx->LX[r].data(), W * 8);
+    if (LZ)
+        for (size_t r = 0; r < ctx->LZ.size(); ++r) std::memcpy(LZ + r * W, ctx->LZ[r].data(), W * 8);
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_edge_counts(mbbp_ctx *ctx, int32_t part, int64_t *edges) {
+    if (!ctx || !edges) return fail(MBBP_EINVAL, "null argument");
+    if (part != 0 && part != 1) return fail(MBBP_EINVAL, "part must be 0 or 1");
+    for (int l = 0; l < ctx->hp[part].L; ++l) edges[l] = ctx->hp[part].E[l];
+    return MBBP_OK;
+}
+
+}  // extern "C"

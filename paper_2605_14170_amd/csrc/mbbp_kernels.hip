@@ -1,0 +1,828 @@
+// HIP kernels of the MBBP-LD library for gfx950 (CDNA4, wave64).
+//
+//  sample_kernel  : counter-based depolarizing noise and syndromes
+//  bp_kernel      : BP on the L representations [H; H_t] (eqs. (1)-(2), Section II-B),
+//                   flooding schedule, normalized min-sum or sum-product; plain
+//                   (one work item per wave) and persistent (atomic work queue with
+//                   per-instance refill) forms share this one kernel
+//  select_kernel  : list decision per shot (Algorithm 1 decision phase, Section III-B)
+//  fail_kernel    : logical-failure test of the residual (Section II-A)
+//
+// Work decomposition of bp_kernel: a wavefront owns G = 64 / LPI instances
+// (shots) of ONE representation; each instance uses LPI lanes.  Lane `lig` of an
+// instance handles checks j = c * LPI + lig and variable slots s = v * LPI + lig
+// (c, v < P, compile-time), so per-lane graph tables and priors live in VGPRs.
+// Per-edge messages live in LDS, one float per edge, in place: the check phase
+// reads v->c messages of its row and overwrites them with c->v messages, the
+// variable phase reads c->v messages and overwrites them with v->c messages.
+// The variable phase also writes its hard decision as a byte at every edge so a
+// check reads its row's decisions with one 8-byte LDS load (syndrome test).
+// Phases are wave-synchronous: no workgroup barrier is ever needed.
+#include <hip/hip_runtime.h>
+
+#include "mbbp_device.h"
+
+#ifndef MBBP_BP_ATTR
+#define MBBP_BP_ATTR
+#endif
+
+namespace mbbp {
+
+// ----------------------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ long long uniform_i64(long long v) {
+    unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffu));
+    unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float bitsf(uint32_t x) { return __uint_as_float(x); }
+
+// ----------------------------------------------------------------------------- Philox4x64-10
+
+// Philox4x64 with 10 rounds (Salmon et al., SC'11): per round two 64x64->128
+// products with multipliers M0, M1, XOR with the neighbouring words and the round
+// key; the key advances by the Weyl constants W0, W1 between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                uint64_t k0, uint64_t k1, uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// ----------------------------------------------------------------------------- sampler
+
+constexpr int kSampleBlock = 64;
+constexpr int kMaxWords = kMaxN / 64;
+
+// One thread per shot.  Error words are staged in LDS as [word][thread] so the
+// syndrome loop (rows are wave-uniform) reads them without bank conflicts.
+__global__ __launch_bounds__(kSampleBlock) void sample_kernel(SampleArgs a) {
+    __shared__ uint64_t sh_e[2][kMaxWords][kSampleBlock];
+    const int t = threadIdx.x;
+    uint64_t seed = a.seed;
+    int64_t shot0 = a.shot0;
+    if (a.desc) { seed = (uint64_t)a.desc[0]; shot0 = a.desc[1]; }
+    const int64_t s = (int64_t)blockIdx.x * kSampleBlock + t;
+    const bool live = s < a.shots;
+    const int n = a.n;
+    const int W = (n + 63) >> 6;
+    for (int w = 0; w < W; ++w) {
+        uint64_t bx = 0, bz = 0;
+        for (int b8 = 0; b8 < 8; ++b8) {
+            const int q0 = w * 64 + b8 * 8;
+            if (q0 >= n) break;
+            uint64_t o[4];
+            philox4x64_10((uint64_t)(shot0 + s), (uint64_t)(q0 >> 3), 0, 0, seed, 0, o);
+#pragma unroll
+            for (int sub = 0; sub < 8; ++sub) {
+                const uint64_t u = (o[sub >> 1] >> (32 * (sub & 1))) & 0xffffffffull;
+                const int bit = b8 * 8 + sub;
+                if (q0 + sub < n) {
+                    const uint64_t xb = (u < a.t2) ? 1ull : 0ull;              // X or Y
+                    const uint64_t zb = (u >= a.t1 && u < a.t3) ? 1ull : 0ull;  // Y or Z
+                    bx |= xb << bit;
+                    bz |= zb << bit;
+                }
+            }
+        }
+        sh_e[0][w][t] = bx;
+        sh_e[1][w][t] = bz;
+        if (live) {
+            a.err[0][s * W + w] = bx;
+            a.err[1][s * W + w] = bz;
+        }
+    }
+    __syncthreads();
+    // part 0: s_X = H_Z e_X (H_Z is part[0]'s matrix); part 1: s_Z = H_X e_Z
+#pragma unroll
+    for (int pt = 0; pt < 2; ++pt) {
+        const DevPart &P = a.part[pt];
+        const int m = P.m, Ws = P.Ws;
+        for (int w = 0; w < Ws; ++w) {
+            uint64_t sw = 0;
+            const int jend = min(m, (w + 1) * 64);
+            for (int j = w * 64; j < jend; ++j) {
+                const int k0 = P.hrow_ptr[j], k1 = P.hrow_ptr[j + 1];
+                uint64_t par = 0;
+                for (int k = k0; k < k1; ++k) {
+                    const int col = P.hrow_idx[k];
+                    par ^= sh_e[pt][col >> 6][t] >> (col & 63);
+                }
+                sw |= (par & 1ull) << (j - w * 64);
+            }
+            if (live) a.syn[pt][s * Ws + w] = sw;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- BP
+
+template <int RULE>
+struct CheckRule;
+
+// Normalized min-sum (eq. (1)) with syndrome sign and clamp: the message to slot k
+// is (-1)^{s_j} * prod_{k' != k} sgn(q_k') * min(alpha * min_{k' != k} |q_k'|, rmax).
+// min over the others is min2 for the (first) minimum and min1 for every other slot.
+template <>
+struct CheckRule<0> {
+    template <int DC>
+    __device__ __forceinline__ static void apply(float (&q)[DC], int sbit, float alpha, float rmax) {
+        float m1 = fminf(fabsf(q[0]), fabsf(q[1]));
+        float m2 = fmaxf(fabsf(q[0]), fabsf(q[1]));
+        uint32_t sx = fbits(q[0]) ^ fbits(q[1]);
+#pragma unroll
+        for (int k = 2; k < DC; ++k) {
+            const float a = fabsf(q[k]);
+            m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
+            m1 = fminf(m1, a);
+            sx ^= fbits(q[k]);
+        }
+        const float A1 = fminf(alpha * m1, rmax);
+        const float A2 = fminf(alpha * m2, rmax);
+        const uint32_t sgn = (sx & 0x80000000u) ^ ((uint32_t)sbit << 31);
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const float mag = (fabsf(q[k]) == m1) ? A2 : A1;
+            q[k] = bitsf(fbits(mag) | ((fbits(q[k]) ^ sgn) & 0x80000000u));
+        }
+    }
+};
+
+// Sum-product: pairwise box-plus x [+] y = sgn(x) sgn(y) min(|x|,|y|)
+//   + log(1 + e^{-|x+y|}) - log(1 + e^{-|x-y|}), forward/backward over the row so
+// slot k gets the box-plus of all other slots; syndrome sign; clamp.
+template <>
+struct CheckRule<1> {
+    __device__ __forceinline__ static float boxplus(float x, float y) {
+        const float ax = fabsf(x), ay = fabsf(y);
+        const float mn = fminf(ax, ay);
+        const float s = (fbits(x) ^ fbits(y)) & 0x80000000u ? -1.0f : 1.0f;
+        const float c1 = __logf(1.0f + __expf(-fabsf(x + y)));
+        const float c2 = __logf(1.0f + __expf(-fabsf(x - y)));
+        return s * mn + c1 - c2;
+    }
+    template <int DC>
+    __device__ __forceinline__ static void apply(float (&q)[DC], int sbit, float, float rmax) {
+        float f[DC], b[DC];
+        f[0] = q[0];
+#pragma unroll
+        for (int k = 1; k < DC; ++k) f[k] = boxplus(f[k - 1], q[k]);
+        b[DC - 1] = q[DC - 1];
+#pragma unroll
+        for (int k = DC - 2; k >= 0; --k) b[k] = boxplus(b[k + 1], q[k]);
+        const uint32_t sgn = (uint32_t)sbit << 31;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            float r = (k == 0) ? b[1] : (k == DC - 1) ? f[DC - 2] : boxplus(f[k - 1], b[k + 1]);
+            r = fminf(fmaxf(r, -rmax), rmax);
+            q[k] = bitsf(fbits(r) ^ sgn);
+        }
+    }
+};
+
+struct ItemPos {
+    int part, l;
+    int64_t begin, end;
+};
+
+__device__ __forceinline__ ItemPos decode_item(const BPArgs &a, int64_t item) {
+    const int64_t rank = item / a.n_chunks;
+    const int64_t ch = item - rank * a.n_chunks;
+    const int pl = a.item_order ? a.item_order[rank] : (int)rank;
+    ItemPos p;
+    p.part = a.part0 + pl / a.L;
+    p.l = pl - (pl / a.L) * a.L;
+    p.begin = ch * a.chunk;
+    p.end = min(p.begin + (int64_t)a.chunk, a.shots);
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 ? v[0] : v[1]; }
+
+// Variable rule (eq. (2) and the posterior of Section II-B) for one variable with
+// at most D edges whose ids are packed 16-bit in vo (absent edges point at the
+// instance's sink row): P = mu + sum r and q_k = mu + sum_{k' != k} r_k',
+// accumulated in ascending check order (never P - r_k).  MIXED: the pass holds
+// variables of different degrees, so edges k >= deg read as 0.
+template <int D, bool MIXED>
+__device__ __forceinline__ void var_rule(float *msg, unsigned char *dece, const uint32_t (&vo)[4], int deg,
+                                         float mu, float &P, bool &dec) {
+    float r[D];
+    uint32_t e[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        e[k] = (k & 1) ? (vo[k >> 1] >> 16) : (vo[k >> 1] & 0xffffu);
+        const float x = msg[e[k]];
+        r[k] = (MIXED && k >= deg) ? 0.0f : x;
+    }
+    float q[D];
+    float pre = mu;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float acc = pre;
+#pragma unroll
+        for (int k2 = k + 1; k2 < D; ++k2) acc += r[k2];
+        q[k] = acc;
+        pre += r[k];
+    }
+    dec = pre < 0.0f;
+    P = pre;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        msg[e[k]] = q[k];
+        dece[e[k]] = (unsigned char)dec;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void var_dispatch(bool mixed, float *msg, unsigned char *dece, const uint32_t (&vo)[4],
+                                             int deg, float mu, float &P, bool &dec) {
+    if (mixed) var_rule<D, true>(msg, dece, vo, deg, mu, P, dec);
+    else var_rule<D, false>(msg, dece, vo, deg, mu, P, dec);
+}
+
+// DC: 6 = every row has weight 6 (no padding); 8 = rows of weight 2..8, unused slots
+// hold +FLT_MAX (never a minimum, neutral for box-plus) and decision byte 0.
+// Instance layout in LDS: (Mmax + 1) rows of 8 floats (row Mmax_part is the sink of
+// absent edges), the same rows of 8 decision bytes, then the staging words.
+template <int LPI, int P, int DC, int RULE>
+__global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
+    constexpr int G = 64 / LPI;
+    constexpr uint64_t GMASK = (LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull);
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int g = lane / LPI;
+    const int lig = lane - g * LPI;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *wbase = smem + (size_t)wib * G * a.inst_bytes;
+    float *msg = reinterpret_cast<float *>(wbase + g * a.inst_bytes);
+    unsigned char *dece = wbase + g * a.inst_bytes + a.msg_bytes;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(dece + a.msg_bytes / 4);
+
+    // decision bytes (and the unused row slots) start at zero
+    {
+        uint32_t *w32 = reinterpret_cast<uint32_t *>(wbase);
+        const int nw = G * a.inst_bytes / 4;
+        for (int i = lane; i < nw; i += 64) w32[i] = 0u;
+    }
+    wave_sync();
+
+    int64_t item;
+    if (a.persistent) {
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(a.queue, 1ull);
+        item = uniform_i64((long long)v);
+    } else {
+        item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    }
+    const float alpha = a.alpha, rmax = a.rmax;
+    const int T = a.T;
+    int cur_key = -1;
+
+    // per-lane tables of the current representation (VGPRs)
+    uint32_t voff[P][4];
+    uint32_t vinfo[P];   // variable id | degree << 16
+    int dmaxp[P];        // max degree over the valid slots of pass v (wave-uniform)
+    int dminp[P];        // min degree over the valid slots of pass v (wave-uniform)
+    uint32_t cwp[P];     // row weights (DC == 8 only)
+    float mu[P];
+
+    while (item < a.n_items) {
+        const ItemPos ip = decode_item(a, item);
+        const DevPart *pt = a.dparts + ip.part;
+        const int n = pt->n, m = pt->m, Mmax = pt->Mmax, W = pt->W, Ws = pt->Ws, L = pt->L;
+        const int l = ip.l;
+        const int Ml = pt->M[l];
+        const int vp = (n + LPI - 1) / LPI;
+        const int cp = (Ml + LPI - 1) / LPI;
+        const uint32_t sink = (uint32_t)Mmax * 8u;
+        const int key = ip.part * 256 + l;
+        if (key != cur_key) {
+            cur_key = key;
+            const uint4 *vo4 = reinterpret_cast<const uint4 *>(pt->voff) + (size_t)l * n;
+            const uint16_t *vid = pt->vid + (size_t)l * n;
+            const uint8_t *vdg = pt->vdeg + (size_t)l * n;
+#pragma unroll
+            for (int v = 0; v < P; ++v) {
+                const int s = v * LPI + lig;
+                const bool valid = v < vp && s < n;
+                const uint32_t sk2 = sink | (sink << 16);
+                uint4 o = make_uint4(sk2, sk2, sk2, sk2);
+                int deg = 0;
+                uint32_t id = 0;
+                if (valid) {
+                    o = vo4[s];
+                    deg = vdg[s];
+                    id = vid[s];
+                }
+                voff[v][0] = o.x; voff[v][1] = o.y; voff[v][2] = o.z; voff[v][3] = o.w;
+                vinfo[v] = id | ((uint32_t)deg << 16);
+                dmaxp[v] = uniform_i32(wave_max_i32(valid ? deg : 0));
+                dminp[v] = uniform_i32(wave_min_i32(valid ? deg : kMaxVarDegree));
+                if (DC == 8) {
+                    const int j = v * LPI + lig;
+                    cwp[v] = (v < cp && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 0u;
+                }
+            }
+            if (DC == 8) {
+                // unused row slots of every instance region: +FLT_MAX, decision 0
+                for (int gg = 0; gg < G; ++gg) {
+                    float *mg = reinterpret_cast<float *>(wbase + gg * a.inst_bytes);
+                    unsigned char *dg = wbase + gg * a.inst_bytes + a.msg_bytes;
+                    for (int i = lane; i < Mmax * 8; i += 64) {
+                        mg[i] = 3.402823466e38f;
+                        dg[i] = 0;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        const float *prior = pick(a.prior, ip.part);
+        const uint64_t *syn = pick(a.syn, ip.part);
+        uint64_t *cand = pick(a.cand, ip.part);
+        uint16_t *kstat = pick(a.kstat, ip.part);
+        float *llr = pick(a.llr, ip.part);
+        const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
+
+        // per-instance state, identical in the LPI lanes of a group
+        int64_t shot = (ip.begin + g < ip.end) ? ip.begin + g : -1;
+        int64_t cn = min(ip.begin + G, ip.end);
+        const int64_t ce = ip.end;
+        bool need_fill = shot >= 0;
+        int it = 0, kfix = -1;
+        uint32_t sbits = 0, decb = 0;
+
+        while (true) {
+            if (__ballot(need_fill) != 0ull) {
+#pragma unroll
+                for (int v = 0; v < P; ++v)
+                    asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
+                                 "+v"(vinfo[v]));
+                if (need_fill) {
+                    // priors of this shot's variables, syndrome bits of this lane's checks,
+                    // and every check->variable message of the instance set to 0
+                    const float *pr = prior + (a.prior_per_shot ? shot * n : 0);
+#pragma unroll
+                    for (int v = 0; v < P; ++v) {
+                        const int s = v * LPI + lig;
+                        mu[v] = (v < vp && s < n) ? pr[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
+                        if (v < vp) {
+#pragma unroll
+                            for (int k = 0; k < kMaxVarDegree; ++k)
+                                if (k < uniform_i32(dmaxp[v])) {
+                                    const uint32_t e = (k & 1) ? (voff[v][k >> 1] >> 16) : (voff[v][k >> 1] & 0xffffu);
+                                    msg[e] = 0.0f;
+                                }
+                        }
+                    }
+                    const uint64_t *sy = syn + shot * Ws;
+                    uint32_t sb = 0;
+#pragma unroll
+                    for (int c = 0; c < P; ++c) {
+                        const int j = c * LPI + lig;
+                        if (c < cp && j < Ml) {
+                            const int src = j < m ? j : csrc[j];
+                            uint32_t bit = 0;
+                            if (src >= 0) {
+                                bit = (uint32_t)(sy[src >> 6] >> (src & 63)) & 1u;
+                            } else {
+                                for (int t = pt->comb_ptr[-src - 1]; t < pt->comb_ptr[-src]; ++t) {
+                                    const int r = pt->comb_idx[t];
+                                    bit ^= (uint32_t)(sy[r >> 6] >> (r & 63)) & 1u;
+                                }
+                            }
+                            sb |= bit << c;
+                        }
+                    }
+                    sbits = sb;
+                    it = 0;
+                    kfix = -1;
+                    need_fill = false;
+                }
+            }
+            if (__ballot(shot >= 0) == 0ull) break;
+            const bool active = shot >= 0;
+            // Keep the packed edge tables opaque to loop-invariant code motion: unpacking
+            // them here costs one ALU op per edge, hoisting would cost 4x the VGPRs.
+#pragma unroll
+            for (int v = 0; v < P; ++v)
+                asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
+                             "+v"(vinfo[v]));
+
+            // ---------------- variable phase: posteriors, decisions, v->c exclusion sums
+#pragma unroll
+            for (int v = 0; v < P; ++v) {
+                if (v < vp) {
+                    const int deg = (int)(vinfo[v] >> 16);
+                    const int dmx = uniform_i32(dmaxp[v]);
+                    const bool mixed = uniform_i32(dminp[v]) != dmx;
+                    float Pv = 0.0f;
+                    bool d = false;
+                    switch (dmx) {
+                    case 1: case 2: var_dispatch<2>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 3: var_dispatch<3>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 4: var_dispatch<4>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 5: var_dispatch<5>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 6: var_dispatch<6>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 7: case 8: var_dispatch<8>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    default: Pv = mu[v]; d = Pv < 0.0f; break;
+                    }
+                    decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
+                    if (llr) {
+                        const int s = v * LPI + lig;
+                        if (active && s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            wave_sync();
+
+            // ---------------- check phase: syndrome test of the decisions, c->v messages.
+            // Slots beyond the representation's checks work on the sink row (garbage in,
+            // garbage out) and do not count in the syndrome test.
+            uint32_t unsat = 0;
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                if (c < cp) {
+                    const int jr = c * LPI + lig;
+                    const int j = jr < Ml ? jr : Mmax;
+                    float *row = msg + j * 8;
+                    const uint2 dd = *reinterpret_cast<const uint2 *>(dece + j * 8);
+                    const uint32_t sb = (sbits >> c) & 1u;
+                    unsat |= ((__popc(dd.x) + __popc(dd.y) + sb) & 1u) & (jr < Ml ? 1u : 0u);
+                    float q[DC];
+                    const float4 q0 = *reinterpret_cast<const float4 *>(row);
+                    q[0] = q0.x; q[1] = q0.y; q[2] = q0.z; q[3] = q0.w;
+                    if constexpr (DC == 6) {
+                        const float2 q1 = *reinterpret_cast<const float2 *>(row + 4);
+                        q[4] = q1.x; q[5] = q1.y;
+                    } else {
+                        const float4 q1 = *reinterpret_cast<const float4 *>(row + 4);
+                        q[4] = q1.x; q[5] = q1.y; q[6] = q1.z; q[7] = q1.w;
+                    }
+                    CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
+                    if constexpr (DC == 6) {
+                        *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
+                        *reinterpret_cast<float2 *>(row + 4) = make_float2(q[4], q[5]);
+                    } else {
+                        const int w = (int)cwp[c];
+#pragma unroll
+                        for (int k = 2; k < DC; ++k)
+                            if (k >= w) q[k] = 3.402823466e38f;
+                        *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
+                        *reinterpret_cast<float4 *>(row + 4) = make_float4(q[4], q[5], q[6], q[7]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const uint64_t um = __ballot(unsat != 0u);
+            const bool gunsat = ((um >> (g * LPI)) & GMASK) != 0ull;
+
+            // ---------------- halting (Section II-B): syndrome met, or the iteration cap
+            bool finish = false, conv = false;
+            int K = 0;
+            if (active) {
+                if (!a.fixed_T) {
+                    if (!gunsat) { finish = true; conv = true; K = it; }
+                    else if (it == T) { finish = true; conv = false; K = T; }
+                    else ++it;
+                } else {
+                    if (!gunsat && kfix < 0) kfix = it;
+                    if (it == T) { finish = true; conv = kfix >= 0; K = conv ? kfix : T; }
+                    else ++it;
+                }
+            }
+            wave_sync();
+            if (__ballot(finish) != 0ull) {
+                // hard decisions -> bit-packed candidate via the instance's staging words
+                if (finish && lig < 2 * W) stage[lig] = 0u;
+                wave_sync();
+                if (finish) {
+#pragma unroll
+                    for (int v = 0; v < P; ++v) {
+                        const int s = v * LPI + lig;
+                        if (v < vp && s < n && ((decb >> v) & 1u)) {
+                            const uint32_t id = vinfo[v] & 0xffffu;
+                            atomicOr(&stage[id >> 5], 1u << (id & 31));
+                        }
+                    }
+                }
+                wave_sync();
+                if (finish) {
+                    const size_t inst = (size_t)shot * L + l;
+                    if (lig < W) cand[inst * W + lig] = reinterpret_cast<const uint64_t *>(stage)[lig];
+                    if (lig == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
+                    shot = -1;
+                }
+                wave_sync();
+                // refill finished instances from the item's remaining shots, in group order
+                const uint64_t freem = __ballot(shot < 0 && lig == 0);
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) {
+                    if (((freem >> (gg * LPI)) & 1ull) && cn < ce) {
+                        if (g == gg) {
+                            shot = cn;
+                            need_fill = true;
+                        }
+                        ++cn;
+                    }
+                }
+            }
+        }
+
+        if (a.persistent) {
+            unsigned long long v = 0;
+            if (lane == 0) v = atomicAdd(a.queue, 1ull);
+            item = uniform_i64((long long)v);
+        } else {
+            item = a.n_items;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- select
+
+__device__ __forceinline__ int popc_words(const uint64_t *w, int W) {
+    int c = 0;
+    for (int i = 0; i < W; ++i) c += __popcll(w[i]);
+    return c;
+}
+
+__device__ __forceinline__ bool words_equal(const uint64_t *x, const uint64_t *y, int W) {
+    for (int i = 0; i < W; ++i)
+        if (x[i] != y[i]) return false;
+    return true;
+}
+
+// One thread per (part, shot): decision over the converged representations.
+__global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = a.shots * a.nparts;
+    long long c_sumk = 0, c_edges = 0, c_noconv = 0, c_ties = 0;
+    if (idx < total) {
+        const int part = a.part0 + (int)(idx / a.shots);
+        const int64_t shot = idx - (int64_t)(part - a.part0) * a.shots;
+        const DevPart &pt = a.part[part];
+        const int L = pt.L, W = pt.W;
+        const uint64_t *cand = a.cand[part] + (size_t)shot * L * W;
+        const uint16_t *ks = a.kstat[part] + (size_t)shot * L;
+        uint64_t convm = 0;
+        int best = -1, bw = 0x7fffffff, kmax = 0;
+        for (int l = 0; l < L; ++l) {
+            const int st = ks[l];
+            const int K = st & 0x7fff;
+            c_sumk += K;
+            c_edges += (long long)K * pt.E[l];
+            kmax = max(kmax, K);
+            if (st & 0x8000) {
+                convm |= 1ull << l;
+                if (a.rule == 0) {
+                    const int w = popc_words(cand + (size_t)l * W, W);
+                    if (w < bw) { bw = w; best = l; }
+                }
+            }
+        }
+        if (a.rule == 1) {
+            // FWS: argmax count(e) / (w(e) + 1), exact cross-multiplied comparison,
+            // ties to the smaller index of first occurrence
+            long long bc = 0, bw1 = 1;
+            for (int l = 0; l < L; ++l) {
+                if (!((convm >> l) & 1ull)) continue;
+                const uint64_t *cl = cand + (size_t)l * W;
+                bool first = true;
+                for (int k = 0; k < l && first; ++k)
+                    if (((convm >> k) & 1ull) && words_equal(cand + (size_t)k * W, cl, W)) first = false;
+                if (!first) continue;
+                long long cnt = 0;
+                for (int k = l; k < L; ++k)
+                    if (((convm >> k) & 1ull) && words_equal(cand + (size_t)k * W, cl, W)) ++cnt;
+                const long long w1 = popc_words(cl, W) + 1;
+                if (best < 0 || cnt * bw1 > bc * w1) { best = l; bc = cnt; bw1 = w1; }
+            }
+        }
+        if (a.counters) {
+            if (best < 0) {
+                c_noconv = 1;
+            } else if (a.rule == 0) {
+                const uint64_t *cb = cand + (size_t)best * W;
+                for (int l = best + 1; l < L; ++l) {
+                    if (((convm >> l) & 1ull) && popc_words(cand + (size_t)l * W, W) == bw &&
+                        !words_equal(cand + (size_t)l * W, cb, W)) { c_ties = 1; break; }
+                }
+            }
+            if (a.kmax_shot) atomicMax(&a.kmax_shot[shot], kmax);
+        }
+        uint64_t *co = a.corr[part] + (size_t)shot * W;
+        for (int w = 0; w < W; ++w) co[w] = best >= 0 ? cand[(size_t)best * W + w] : 0ull;
+        a.conv[part][shot] = convm;
+        a.basis[part][shot] = (int16_t)best;
+    }
+    if (a.counters) {
+        c_sumk = wave_sum_i64(c_sumk);
+        c_edges = wave_sum_i64(c_edges);
+        c_noconv = wave_sum_i64(c_noconv);
+        c_ties = wave_sum_i64(c_ties);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd((unsigned long long *)&a.counters[4], (unsigned long long)c_sumk);
+            atomicAdd((unsigned long long *)&a.counters[5], (unsigned long long)c_edges);
+            atomicAdd((unsigned long long *)&a.counters[6], (unsigned long long)c_noconv);
+            atomicAdd((unsigned long long *)&a.counters[7], (unsigned long long)c_ties);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------- failures
+
+// One thread per shot.  Part X: residual r = e_X ^ corr_x fails iff H_Z r != 0 or
+// L_Z r != 0 (it is then not a product of X stabilizers); part Z symmetric.
+// part[0] holds H_Z and L_Z, part[1] holds H_X and L_X.
+__global__ __launch_bounds__(256) void fail_kernel(FailArgs a) {
+    const int64_t shot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long c_fail = 0, c_fx = 0, c_fz = 0, c_kmax = 0;
+    if (shot < a.shots) {
+        uint32_t flags = 0;
+        for (int pt = 0; pt < 2; ++pt) {
+            const DevPart &P = a.part[pt];
+            const int W = P.W;
+            const uint64_t *e = a.err[pt] + (size_t)shot * W;
+            const uint64_t *c = a.corr[pt] + (size_t)shot * W;
+            bool bad = false;
+            for (int j = 0; j < P.m && !bad; ++j) {
+                uint32_t par = 0;
+                for (int k = P.hrow_ptr[j]; k < P.hrow_ptr[j + 1]; ++k) {
+                    const int col = P.hrow_idx[k];
+                    par ^= (uint32_t)((e[col >> 6] ^ c[col >> 6]) >> (col & 63)) & 1u;
+                }
+                bad = par != 0;
+            }
+            for (int r = 0; r < P.k && !bad; ++r) {
+                int cnt = 0;
+                for (int w = 0; w < W; ++w) cnt += __popcll((e[w] ^ c[w]) & P.logical[(size_t)r * W + w]);
+                bad = (cnt & 1) != 0;
+            }
+            if (bad) flags |= 1u << pt;
+        }
+        if (a.fail) a.fail[shot] = (uint8_t)flags;
+        c_fail = flags != 0;
+        c_fx = flags & 1u;
+        c_fz = (flags >> 1) & 1u;
+        if (a.kmax_shot) c_kmax = a.kmax_shot[shot];
+    }
+    if (a.counters) {
+        c_fail = wave_sum_i64(c_fail);
+        c_fx = wave_sum_i64(c_fx);
+        c_fz = wave_sum_i64(c_fz);
+        c_kmax = wave_sum_i64(c_kmax);
+        if ((threadIdx.x & 63) == 0) {
+            atomicAdd((unsigned long long *)&a.counters[0], (unsigned long long)c_fail);
+            atomicAdd((unsigned long long *)&a.counters[1], (unsigned long long)c_fx);
+            atomicAdd((unsigned long long *)&a.counters[2], (unsigned long long)c_fz);
+            atomicAdd((unsigned long long *)&a.counters[3], (unsigned long long)c_kmax);
+        }
+    }
+}
+
+__global__ void reset_kernel(unsigned long long *queue, int64_t *counters, int nc) {
+    const int t = threadIdx.x;
+    if (queue && t == 0) *queue = 0ull;
+    if (counters && t < nc) counters[t] = 0;
+}
+
+// ----------------------------------------------------------------------------- launchers
+
+hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
+    const int64_t blocks = (a.shots + kSampleBlock - 1) / kSampleBlock;
+    hipLaunchKernelGGL(sample_kernel, dim3((unsigned)blocks), dim3(kSampleBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectArgs &a, hipStream_t s) {
+    const int64_t total = a.shots * a.nparts;
+    hipLaunchKernelGGL(select_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fail(const FailArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(fail_kernel, dim3((unsigned)((a.shots + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncounters, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, queue, counters, ncounters);
+    return hipGetLastError();
+}
+
+size_t bp_lds_limit() { return 64 * 1024; }  // per workgroup
+
+// Instantiated (LPI, P) pairs: P = register slots per lane for checks and variables.
+static const int kP16[] = {3, 6, 9};
+static const int kP32[] = {3, 5, 9};
+static const int kP64[] = {2, 3, 5, 9, 14, 16};
+
+static int pick_passes(int lpi, int need) {
+    const int *lst = lpi == 16 ? kP16 : (lpi == 32 ? kP32 : kP64);
+    const int cnt = lpi == 64 ? 6 : 3;
+    for (int i = 0; i < cnt; ++i)
+        if (lst[i] >= need) return lst[i];
+    return -1;
+}
+
+int bp_max_passes(int lpi) { return lpi == 64 ? 16 : 9; }
+
+static int passes_needed(const BPArgs &a, int lpi) {
+    int need = 1;
+    for (int p = a.part0; p < a.part0 + a.nparts; ++p) {
+        need = max(need, (a.part[p].n + lpi - 1) / lpi);
+        need = max(need, (a.part[p].Mmax + lpi - 1) / lpi);
+    }
+    return need;
+}
+
+bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule) {
+    (void)dc_uniform;
+    if (schedule != 0) return false;
+    if (rule != 0 && rule != 1) return false;
+    if (lpi != 16 && lpi != 32 && lpi != 64) return false;
+    return pick_passes(lpi, passes) > 0;
+}
+
+template <int LPI, int P, int DC, int RULE>
+static hipError_t launch_bp_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
+    const int wpb = cfg.waves_per_block;
+    const size_t lds = (size_t)wpb * (64 / LPI) * a.inst_bytes;
+    int64_t blocks;
+    if (a.persistent) blocks = cfg.blocks;
+    else blocks = (a.n_items + wpb - 1) / wpb;
+    hipLaunchKernelGGL((bp_kernel<LPI, P, DC, RULE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int LPI, int P>
+static hipError_t launch_bp_p(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
+    bool u6 = true;
+    for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
+    if (rule == 0) return u6 ? launch_bp_t<LPI, P, 6, 0>(a, cfg, s) : launch_bp_t<LPI, P, 8, 0>(a, cfg, s);
+    return u6 ? launch_bp_t<LPI, P, 6, 1>(a, cfg, s) : launch_bp_t<LPI, P, 8, 1>(a, cfg, s);
+}
+
+hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s) {
+    if (schedule != 0) return hipErrorInvalidValue;
+    const int P = pick_passes(cfg.lpi, passes_needed(a, cfg.lpi));
+#ifndef MBBP_KERNEL_PROBE
+    switch (cfg.lpi * 100 + P) {
+    case 1603: return launch_bp_p<16, 3>(a, cfg, rule, s);
+    case 1606: return launch_bp_p<16, 6>(a, cfg, rule, s);
+    case 1609: return launch_bp_p<16, 9>(a, cfg, rule, s);
+    case 3203: return launch_bp_p<32, 3>(a, cfg, rule, s);
+    case 3205: return launch_bp_p<32, 5>(a, cfg, rule, s);
+    case 3209: return launch_bp_p<32, 9>(a, cfg, rule, s);
+    case 6402: return launch_bp_p<64, 2>(a, cfg, rule, s);
+    case 6403: return launch_bp_p<64, 3>(a, cfg, rule, s);
+    case 6405: return launch_bp_p<64, 5>(a, cfg, rule, s);
+    case 6409: return launch_bp_p<64, 9>(a, cfg, rule, s);
+    case 6414: return launch_bp_p<64, 14>(a, cfg, rule, s);
+    case 6416: return launch_bp_p<64, 16>(a, cfg, rule, s);
+    }
+#else
+    (void)P; (void)rule; (void)s;
+#endif
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mbbp

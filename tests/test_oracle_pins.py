@@ -80,10 +80,10 @@ def test_sampler_against_numpy_philox_and_matmul():
                     bz[s, q] = 1
     np.testing.assert_array_equal(oracle.unpack(ex, n), bx)
     np.testing.assert_array_equal(oracle.unpack(ez, n), bz)
-    np.testing.assert_array_equal(oracle.unpack(sx, code.hx.shape[0]),
-                                  (bz.astype(np.int64) @ code.hx.T.astype(np.int64)) % 2)
-    np.testing.assert_array_equal(oracle.unpack(sz, code.hz.shape[0]),
+    np.testing.assert_array_equal(oracle.unpack(sx, code.hz.shape[0]),
                                   (bx.astype(np.int64) @ code.hz.T.astype(np.int64)) % 2)
+    np.testing.assert_array_equal(oracle.unpack(sz, code.hx.shape[0]),
+                                  (bz.astype(np.int64) @ code.hx.T.astype(np.int64)) % 2)
 
 
 def test_sampler_frequencies():
@@ -407,7 +407,7 @@ def test_small_codes_against_brute_force(factory):
     ex, ez, sx, sz = oracle.sample(c.hx, c.hz, 3, 0.12, 0, 300)
     mu = np.full(n, oracle.prior_llr(0.12))
     all_e = np.array(list(itertools.product([0, 1], repeat=n)), np.int64)
-    for h, stab, perms, syn, err in ((c.hz, c.hx, perms_z, sz, ex), (c.hx, c.hz, perms_x, sx, ez)):
+    for h, stab, perms, syn, err in ((c.hz, c.hx, perms_z, sx, ex), (c.hx, c.hz, perms_x, sz, ez)):
         L = 2
         bp, rows = oracle.build_bases(h, "ramp", L, perms)
         res = oracle.decode(h, bp, rows, syn, mu, T=15, alpha=0.875)
