@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the MBBP-LD hot path on one MI355X.
+
+One step = the whole path over one batch of the [[144,12,12]] workload: for every
+error rate p in {0.02, 0.04, 0.06, 0.08}, `shots` (default 10^6) shots of
+code-capacity depolarizing noise generated on the GPU, their syndromes, BP
+(normalized min-sum, flooding, T = 50, alpha = 0.875) on the 16 subtree
+representations of each of H_X and H_Z, the least-weight decision and the
+logical-failure test, accumulated into device counters.  Inputs are synthetic
+and generated inside the timed region (the noise sampler is one of the path's
+steps); nothing is cached between steps (each step decodes fresh shot indices).
+
+Prints one JSON line.  `value` is decoded shots per second; the edge-message
+update rate, the roofline of the BP kernel (from HIP events recorded around every
+BP launch on its stream) and the CPU oracle baseline ride along.
+"""
+
+from __future__ import annotations
+
+import argparse
+import concurrent.futures
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic VALU lane-operations per edge-message update of normalized min-sum
+# (two-minimum tracking 2, sign parity 1, minimum test and select 2, sign apply 1,
+# per-check scaling and clamp ~0.7, posterior and message sums 2, syndrome parity 1,
+# decision ~0.3); see the design doc.
+OPS_PER_EDGE_UPDATE = 10.0
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed 32-bit VALU lane-ops)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="bb144_L16_T50")
+    ap.add_argument("--shots", type=int, default=None, help="shots per error rate per step")
+    ap.add_argument("--form", choices=["batched", "plain"], default="batched")
+    ap.add_argument("--lpi", type=int, default=0, help="lanes per BP instance (0 = library choice)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-shots", type=int, default=1500, help="oracle sample: shots per error rate")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def build_decoder(pk, wl, code, max_batch):
+    from workloads.perms import check_permutations
+    perms = lambda h: check_permutations(h.shape[0], max(wl.L, 8), wl.perm_seed)  # noqa: E731
+    bx = pk.build_bases(code.hx, wl.basis_mode, wl.L, perms(code.hx))
+    bz = pk.build_bases(code.hz, wl.basis_mode, wl.L, perms(code.hz))
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, wl.T, alpha=wl.alpha, max_batch=max_batch)
+    return dec, bx, bz
+
+
+def cpu_baseline(wl, code, bx, bz, shots_per_p, threads):
+    """The oracle as it stands (FP64, single-threaded per call) on `threads` host
+    threads over disjoint shot ranges of the same workload."""
+    import oracle
+    chunk = max(1, shots_per_p // threads)
+    jobs = []
+    for p in wl.ps:
+        for start in range(0, shots_per_p, chunk):
+            jobs.append((p, start, min(chunk, shots_per_p - start)))
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(lambda j: oracle.run(code, bx, bz, wl.seed, j[0], 10**12 + j[1], j[2], wl.T, wl.alpha),
+                          jobs))
+    dt = time.perf_counter() - t0
+    shots = sum(r.shots for r in res)
+    edges = sum(r.edge_updates for r in res)
+    return dict(value=shots / dt, unit="shots/s", cores=threads, kind="oracle",
+                edge_updates_per_s=edges / dt, seconds=dt,
+                sample=f"{shots_per_p} shots at each p in {list(wl.ps)} ({shots} shots), FP64 oracle, "
+                       f"{threads} threads over disjoint shot ranges")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              f"design (shot sharding, one all-reduce of counters) is described in DESIGN.md "
+              f"and not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2605_14170_amd as pk
+    from workloads.configs import WORKLOADS
+
+    wl = WORKLOADS[args.workload]
+    code = wl.code()
+    shots = args.shots or wl.shots
+    torch.cuda.set_device(0)
+    dec, bx, bz = build_decoder(pk, wl, code, shots)
+    ps = list(wl.ps)
+    stream = torch.cuda.current_stream()
+
+    def step(k, counters):
+        for i, p in enumerate(ps):
+            base = (k * len(ps) + i) * shots
+            if args.form == "batched":
+                dec.run(wl.seed, p, base, shots, counters[i], stream)
+            else:
+                ex, ez, sx, sz = dec.sample(wl.seed, p, base, shots, stream)
+                prior = torch.full((code.n,), pk.prior_llr(p), dtype=torch.float32, device="cuda")
+                out = dec.decode(sx, sz, prior, prior, stream)
+                dec.failures(ex, ez, out["corr_x"], out["corr_z"], stream)
+
+    print(f"# workload {wl.key}: {wl.description}; shots/p/step {shots}", file=sys.stderr, flush=True)
+    warm = torch.zeros((len(ps), pk.NUM_COUNTERS), dtype=torch.int64, device="cuda")
+    for k in range(args.warmup):
+        step(10_000 + k, warm)
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+    counters = torch.zeros((len(ps), pk.NUM_COUNTERS), dtype=torch.int64, device="cuda")
+    dec.bp_time(reset=True)
+    dec.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k, counters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dec.set_timing(False)
+    bp_ms, bp_launches = dec.bp_time(reset=True)
+    c = counters.cpu().numpy()
+    total_shots = shots * len(ps) * args.steps
+    edges = int(c[:, pk.CNT_EDGE_UPDATES].sum())
+    ms_per_step = dt * 1e3 / args.steps
+    value = total_shots / dt
+    per_p = {str(p): dict(ler=float(c[i, pk.CNT_FAIL]) / (shots * args.steps),
+                          mean_kmax=float(c[i, pk.CNT_SUM_KMAX]) / (shots * args.steps),
+                          mean_k=float(c[i, pk.CNT_SUM_K]) / (shots * args.steps * 2 * wl.L),
+                          noconv_frac=float(c[i, pk.CNT_NOCONV]) / (shots * args.steps * 2))
+             for i, p in enumerate(ps)}
+    print(f"# timed {args.steps} steps in {dt:.3f} s; BP kernel {bp_ms:.1f} ms over {bp_launches} launches",
+          file=sys.stderr, flush=True)
+    bp_avg_s = bp_ms / 1e3 / max(1, bp_launches)
+    edges_per_launch = edges / max(1, bp_launches)
+    achieved = edges_per_launch * OPS_PER_EDGE_UPDATE / bp_avg_s / 1e12 if bp_launches else None
+    roofline = dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="T lane-op/s",
+                    frac=(achieved / VALU_PEAK_TOPS) if achieved else None, traffic=None,
+                    kernel="bp_kernel", avg_launch_ms=bp_avg_s * 1e3,
+                    edge_updates_per_launch=edges_per_launch,
+                    ops_per_edge_update=OPS_PER_EDGE_UPDATE)
+    line = dict(metric="MBBP-LD decoded shots/s and BP edge-msg updates/s at matched logical error rate",
+                value=value, unit="shots/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32", data="synthetic",
+                config=dict(workload=wl.key, code=code.name, n=code.n, L=wl.L, T=wl.T, alpha=wl.alpha,
+                            ps=ps, shots_per_p=shots, schedule="flooding", rule="normalized min-sum",
+                            form=args.form, basis_mode=wl.basis_mode),
+                edge_updates_per_s=edges / dt, per_p=per_p, roofline=roofline)
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        print(f"# cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
+        import oracle
+        obx = oracle.build_bases(code.hx, wl.basis_mode, wl.L,
+                                 __import__("workloads").check_permutations(code.hx.shape[0], max(wl.L, 8),
+                                                                             wl.perm_seed))
+        obz = oracle.build_bases(code.hz, wl.basis_mode, wl.L,
+                                 __import__("workloads").check_permutations(code.hz.shape[0], max(wl.L, 8),
+                                                                             wl.perm_seed))
+        line["cpu_baseline"] = cpu_baseline(wl, code, obx, obz, args.cpu_shots, threads)
+    dec.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -183,6 +183,13 @@ enum {
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
                      int64_t *counters, void *hip_stream);
 
+/* Event timing of the BP kernel.  While enabled, every BP kernel launch of this
+ * context is bracketed by HIP events recorded on the launch's stream.
+ * mbbp_bp_time waits for those events and returns the summed elapsed time (ms)
+ * and the number of launches since the last reset (reset != 0 clears them). */
+mbbp_status mbbp_set_timing(mbbp_ctx *ctx, int32_t enable);
+mbbp_status mbbp_bp_time(mbbp_ctx *ctx, double *ms, int64_t *launches, int32_t reset);
+
 /* Algorithm 2 on host memory: perm is a permutation of the m checks (root
  * order); check_sets[m] receives the 1-based subtree of each check, order[m]
  * the checks in acceptance order (subtree 1 first), *n_subtrees their number. */

@@ -119,7 +119,8 @@ def philox4x64_10(ctr: Sequence[int], key: Sequence[int], precision: str = "f64"
 
 def sample(hx: np.ndarray, hz: np.ndarray, seed: int, p: float, shot0: int, shots: int):
     """Depolarizing errors and syndromes for shots [shot0, shot0 + shots).
-    Returns (e_x, e_z, s_x, s_z) as bit-packed uint64 arrays."""
+    Returns (e_x, e_z, s_x, s_z) as bit-packed uint64 arrays, named by error
+    type: s_x = H_Z e_x (m_Z bits), s_z = H_X e_z (m_X bits)."""
     lib = _lib("f64")
     n = hx.shape[1]
     xp, xi = csr(hx)
@@ -127,8 +128,8 @@ def sample(hx: np.ndarray, hz: np.ndarray, seed: int, p: float, shot0: int, shot
     wn, wx, wz = words64(n), words64(hx.shape[0]), words64(hz.shape[0])
     ex = np.zeros((shots, wn), np.uint64)
     ez = np.zeros((shots, wn), np.uint64)
-    sx = np.zeros((shots, wx), np.uint64)
-    sz = np.zeros((shots, wz), np.uint64)
+    sx = np.zeros((shots, wz), np.uint64)
+    sz = np.zeros((shots, wx), np.uint64)
     _check(lib.orc_sample(n, hx.shape[0], _ptr(xp), _ptr(xi), hz.shape[0], _ptr(zp), _ptr(zi),
                           int(seed), float(p), int(shot0), int(shots),
                           _ptr(ex), _ptr(ez), _ptr(sx), _ptr(sz)), "sample")
@@ -319,9 +320,10 @@ def run(code, bases_x, bases_z, seed: int, p: float, shot0: int, shots: int, T: 
     kmax = np.zeros(shots, np.int64)
     sum_k = 0
     edges = 0
-    # X errors are seen by H_Z (s_Z = H_Z e_X); Z errors by H_X.
-    for h, (bp, rows), syn, err, stab in ((code.hz, bases_z, sz, ex, code.hx),
-                                           (code.hx, bases_x, sx, ez, code.hz)):
+    # part X: e_x, s_x = H_Z e_x, representations of H_Z (bases_z), stabilizers H_X;
+    # part Z: e_z, s_z = H_X e_z, representations of H_X (bases_x), stabilizers H_Z.
+    for h, (bp, rows), syn, err, stab in ((code.hz, bases_z, sx, ex, code.hx),
+                                           (code.hx, bases_x, sz, ez, code.hz)):
         res = decode(h, bp, rows, syn, np.full(n, mu32), T, schedule, rule, alpha, rmax,
                      select_rule=select_rule, precision=precision)
         fails |= failures(stab, err, res.corr)

@@ -129,14 +129,14 @@ int orc_sample(int n, int mx, const int *hx_ptr, const int *hx_idx,
                 setbit(ezs, q);
             }
         }
-        /* s_X = H_X e_Z ; s_Z = H_Z e_X */
-        uint64_t *sxs = sx + s * wx, *szs = sz + s * wz;
-        memset(sxs, 0, sizeof(uint64_t) * (size_t)wx);
-        memset(szs, 0, sizeof(uint64_t) * (size_t)wz);
-        for (int j = 0; j < mx; ++j)
-            if (parity_row(hx_idx + hx_ptr[j], hx_ptr[j + 1] - hx_ptr[j], ezs)) setbit(sxs, j);
+        /* named by error type: s_X = H_Z e_X (m_Z bits), s_Z = H_X e_Z (m_X bits) */
+        uint64_t *sxs = sx + s * wz, *szs = sz + s * wx;
+        memset(sxs, 0, sizeof(uint64_t) * (size_t)wz);
+        memset(szs, 0, sizeof(uint64_t) * (size_t)wx);
         for (int j = 0; j < mz; ++j)
-            if (parity_row(hz_idx + hz_ptr[j], hz_ptr[j + 1] - hz_ptr[j], exs)) setbit(szs, j);
+            if (parity_row(hz_idx + hz_ptr[j], hz_ptr[j + 1] - hz_ptr[j], exs)) setbit(sxs, j);
+        for (int j = 0; j < mx; ++j)
+            if (parity_row(hx_idx + hx_ptr[j], hx_ptr[j + 1] - hx_ptr[j], ezs)) setbit(szs, j);
     }
     return ORC_OK;
 }

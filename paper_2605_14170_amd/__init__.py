@@ -240,6 +240,17 @@ class Decoder:
                                             _ptr(corr_z), _ptr(fail), _stream(stream)), "mbbp_failures")
         return fail
 
+    def set_timing(self, enable: bool) -> None:
+        _lib.check(_lib.lib().mbbp_set_timing(self._ctx, 1 if enable else 0), "mbbp_set_timing")
+
+    def bp_time(self, reset: bool = True) -> Tuple[float, int]:
+        """(summed BP kernel milliseconds from HIP events, launches) since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _lib.check(_lib.lib().mbbp_bp_time(self._ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0),
+                   "mbbp_bp_time")
+        return ms.value, n.value
+
     def run(self, seed: int, p: float, shot0: int, shots: int, counters=None, stream=None):
         torch = _torch()
         if counters is None:

@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
             "mbbp_logicals": ([P, P, P, P], i32),
             "mbbp_edge_counts": ([P, i32, P], i32),
             "mbbp_last_error": ([], ctypes.c_char_p),
+            "mbbp_set_timing": ([P, i32], i32),
+            "mbbp_bp_time": ([P, P, P, i32], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -88,4 +90,5 @@ def check(status: int, where: str) -> None:
 
 EXPORTED = ["mbbp_params_default", "mbbp_create", "mbbp_destroy", "mbbp_decode", "mbbp_decode_batched",
             "mbbp_decode_detail", "mbbp_sample", "mbbp_failures", "mbbp_run", "mbbp_subtrees",
-            "mbbp_build_bases", "mbbp_logicals", "mbbp_edge_counts", "mbbp_last_error"]
+            "mbbp_build_bases", "mbbp_logicals", "mbbp_edge_counts", "mbbp_last_error", "mbbp_set_timing",
+            "mbbp_bp_time"]

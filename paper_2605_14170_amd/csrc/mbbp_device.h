@@ -111,6 +111,10 @@ hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_fail(const FailArgs &a, hipStream_t s);
 hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncounters, hipStream_t s);
+// Per-run preparation: uniform priors mu for both parts, per-shot max-iteration
+// scratch cleared, work-queue counter cleared.
+hipError_t launch_run_prep(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
+                           unsigned long long *queue, hipStream_t s);
 int bp_max_passes(int lpi);  // register slots available per lane for this lpi
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();

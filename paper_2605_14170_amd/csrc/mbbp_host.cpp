@@ -373,6 +373,11 @@ struct mbbp_ctx {
     mbbp::BPConfig batched_cfg{16, 4, 8, 0};
     hipStream_t capture_stream = nullptr;
     std::map<int64_t, RunGraph> graphs;
+    // BP kernel event timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
 
     template <typename T>
     mbbp_status alloc(T *&p, size_t count) {
@@ -443,6 +448,22 @@ int inst_bytes_for(const mbbp_ctx *c, int part0, int nparts, int *msg_bytes) {
     return (bytes + 15) & ~15;
 }
 
+mbbp_status ensure_run_workspace(mbbp_ctx *c) {
+    if (c->w_kmax) return MBBP_OK;
+    const int64_t B = c->params.max_batch;
+    mbbp_status st;
+    for (int p = 0; p < 2; ++p) {
+        const int W = c->dp[p].W, Ws = c->dp[p].Ws;
+        if ((st = c->alloc(c->w_err[p], (size_t)B * W)) != MBBP_OK) return st;
+        if ((st = c->alloc(c->w_syn[p], (size_t)B * Ws)) != MBBP_OK) return st;
+        if ((st = c->alloc(c->w_corr[p], (size_t)B * W)) != MBBP_OK) return st;
+        if ((st = c->alloc(c->w_conv[p], (size_t)B)) != MBBP_OK) return st;
+        if ((st = c->alloc(c->w_basis[p], (size_t)B)) != MBBP_OK) return st;
+        if ((st = c->alloc(c->w_prior[p], (size_t)c->n)) != MBBP_OK) return st;
+    }
+    return c->alloc(c->w_kmax, (size_t)B);
+}
+
 mbbp_status check_stream_ptrs(const void *p, const char *what) {
     if (!p) return fail(MBBP_EINVAL, std::string("null pointer: ") + what);
     return MBBP_OK;
@@ -492,8 +513,18 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         run.waves_per_block /= 2;
     if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
         return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->timing) {
+        MBBP_HIP(hipEventCreate(&ev0));
+        MBBP_HIP(hipEventCreate(&ev1));
+        MBBP_HIP(hipEventRecord(ev0, s));
+    }
     hipError_t e = mbbp::launch_bp(a, run, c->schedule, c->params.rule, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("bp launch: ") + hipGetErrorString(e));
+    if (c->timing) {
+        MBBP_HIP(hipEventRecord(ev1, s));
+        c->events.push_back({ev0, ev1});
+    }
     return MBBP_OK;
 }
 
@@ -731,6 +762,10 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
 void mbbp_destroy(mbbp_ctx *ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
+    for (auto &ev : ctx->events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
     for (auto &kv : ctx->graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
@@ -843,8 +878,67 @@ mbbp_status mbbp_failures(mbbp_ctx *ctx, int64_t shots, const uint64_t *err_x, c
 
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, int64_t *counters,
                      void *hip_stream) {
-    (void)ctx; (void)seed; (void)p; (void)shot0; (void)shots; (void)counters; (void)hip_stream;
-    return fail(MBBP_EUNSUPPORTED, "mbbp_run not built yet");
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (!(p > 0.0 && p < 1.5)) return fail(MBBP_EINVAL, "p must be in (0, 1.5) for the uniform prior");
+    if (shots < 1 || shots > ctx->params.max_batch || shot0 < 0) return fail(MBBP_EINVAL, "shots out of range");
+    if (!counters) return fail(MBBP_EINVAL, "null counters");
+    mbbp_status st = ensure_run_workspace(ctx);
+    if (st != MBBP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const double q = 2.0 * p / 3.0;
+    const float mu = (float)std::log((1.0 - q) / q);
+    hipError_t e = mbbp::launch_run_prep(ctx->w_prior[0], ctx->w_prior[1], ctx->n, mu, ctx->w_kmax, shots,
+                                         ctx->w_queue, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("prep launch: ") + hipGetErrorString(e));
+    if ((st = mbbp_sample(ctx, seed, p, shot0, shots, ctx->w_err[0], ctx->w_err[1], ctx->w_syn[0], ctx->w_syn[1],
+                          hip_stream)) != MBBP_OK)
+        return st;
+    const uint64_t *sy[2] = {ctx->w_syn[0], ctx->w_syn[1]};
+    const float *pr[2] = {ctx->w_prior[0], ctx->w_prior[1]};
+    float *ll[2] = {nullptr, nullptr};
+    if ((st = run_bp(ctx, 0, 2, shots, sy, pr, 0, ctx->cand, ctx->kstat, ll, true, s)) != MBBP_OK) return st;
+    if ((st = run_select(ctx, 0, 2, shots, ctx->w_corr, ctx->w_conv, ctx->w_basis, counters, ctx->w_kmax, s)) !=
+        MBBP_OK)
+        return st;
+    mbbp::FailArgs a{};
+    a.part[0] = ctx->dp[0];
+    a.part[1] = ctx->dp[1];
+    a.shots = shots;
+    a.err[0] = ctx->w_err[0]; a.err[1] = ctx->w_err[1];
+    a.corr[0] = ctx->w_corr[0]; a.corr[1] = ctx->w_corr[1];
+    a.fail = nullptr;
+    a.counters = counters;
+    a.kmax_shot = ctx->w_kmax;
+    e = mbbp::launch_fail(a, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("failure launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_set_timing(mbbp_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    ctx->timing = enable != 0;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_bp_time(mbbp_ctx *ctx, double *ms, int64_t *launches, int32_t reset) {
+    if (!ctx || !ms || !launches) return fail(MBBP_EINVAL, "null argument");
+    for (auto &ev : ctx->events) {
+        MBBP_HIP(hipEventSynchronize(ev.second));
+        float t = 0.0f;
+        MBBP_HIP(hipEventElapsedTime(&t, ev.first, ev.second));
+        ctx->timed_ms += t;
+        ctx->timed_launches += 1;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    ctx->events.clear();
+    *ms = ctx->timed_ms;
+    *launches = ctx->timed_launches;
+    if (reset) {
+        ctx->timed_ms = 0.0;
+        ctx->timed_launches = 0;
+    }
+    return MBBP_OK;
 }
 
 mbbp_status mbbp_logicals(mbbp_ctx *ctx, uint64_t *LX, uint64_t *LZ, int32_t *k) {

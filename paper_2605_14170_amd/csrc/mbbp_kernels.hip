@@ -724,7 +724,26 @@ __global__ void reset_kernel(unsigned long long *queue, int64_t *counters, int n
     if (counters && t < nc) counters[t] = 0;
 }
 
+__global__ void run_prep_kernel(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
+                                unsigned long long *queue) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        prior0[i] = mu;
+        prior1[i] = mu;
+    }
+    if (i < shots) kmax[i] = 0;
+    if (i == 0 && queue) *queue = 0ull;
+}
+
 // ----------------------------------------------------------------------------- launchers
+
+hipError_t launch_run_prep(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
+                           unsigned long long *queue, hipStream_t s) {
+    const int64_t total = shots > n ? shots : n;
+    hipLaunchKernelGGL(run_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, prior0, prior1,
+                       n, mu, kmax, shots, queue);
+    return hipGetLastError();
+}
 
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
     const int64_t blocks = (a.shots + kSampleBlock - 1) / kSampleBlock;
