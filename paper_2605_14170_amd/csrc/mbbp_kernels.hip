@@ -269,10 +269,12 @@ __device__ __forceinline__ void var_rule(float *msg, unsigned char *dece, const 
     }
 }
 
+// dmin: smallest degree among the pass's valid variables (wave-uniform).  Masking is
+// needed whenever some valid variable has fewer than D edges.
 template <int D>
-__device__ __forceinline__ void var_dispatch(bool mixed, float *msg, unsigned char *dece, const uint32_t (&vo)[4],
+__device__ __forceinline__ void var_dispatch(int dmin, float *msg, unsigned char *dece, const uint32_t (&vo)[4],
                                              int deg, float mu, float &P, bool &dec) {
-    if (mixed) var_rule<D, true>(msg, dece, vo, deg, mu, P, dec);
+    if (dmin < D) var_rule<D, true>(msg, dece, vo, deg, mu, P, dec);
     else var_rule<D, false>(msg, dece, vo, deg, mu, P, dec);
 }
 
@@ -451,16 +453,16 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                 if (v < vp) {
                     const int deg = (int)(vinfo[v] >> 16);
                     const int dmx = uniform_i32(dmaxp[v]);
-                    const bool mixed = uniform_i32(dminp[v]) != dmx;
+                    const int dmn = uniform_i32(dminp[v]);
                     float Pv = 0.0f;
                     bool d = false;
                     switch (dmx) {
-                    case 1: case 2: var_dispatch<2>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 3: var_dispatch<3>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 4: var_dispatch<4>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 5: var_dispatch<5>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 6: var_dispatch<6>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 7: case 8: var_dispatch<8>(mixed, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 1: case 2: var_dispatch<2>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 3: var_dispatch<3>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 4: var_dispatch<4>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 5: var_dispatch<5>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 6: var_dispatch<6>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
+                    case 7: case 8: var_dispatch<8>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
                     default: Pv = mu[v]; d = Pv < 0.0f; break;
                     }
                     decb = (decb & ~(1u << v)) | ((uint32_t)d << v);

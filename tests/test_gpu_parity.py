@@ -309,3 +309,29 @@ def test_run_counters_match_oracle(pk):
         assert int(cnt[k]) == v, (k, int(cnt[k]), v)
     say(f"  counters {cnt.tolist()}")
     dec.close()
+
+
+@pytest.mark.parametrize("factory", [codes.steane7, codes.surface13, codes.toric18])
+def test_nms_small_codes_padded_rows_bit_exact(pk, factory):
+    """Rows of weight 2..4 (padded row slots) and variables of degree 1..4 (masked
+    variable passes): bit-exact against the FP32 oracle."""
+    from workloads.perms import check_permutations
+    code = factory()
+    L, T, shots, p = 3, 12, 700, 0.1
+    bx = oracle.build_bases(code.hx, "ramp", L, check_permutations(code.hx.shape[0], L, 1))
+    bz = oracle.build_bases(code.hz, "ramp", L, check_permutations(code.hz.shape[0], L, 1))
+    say(f"small code {code.name}: n={code.n}")
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, T, alpha=0.8, max_batch=shots)
+    ex, ez, sx, sz = dec.sample(5, p, 0, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+        torch.cuda.synchronize()
+        ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), T, alpha=0.8, want_llr=True,
+                            precision="f32")
+        ks = kstat.cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(words(cand), ref.cand)
+        np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+    dec.close()
