@@ -46,9 +46,13 @@ def parse():
     ap.add_argument("--shots", type=int, default=None, help="shots per error rate per step")
     ap.add_argument("--form", choices=["batched", "plain"], default="batched")
     ap.add_argument("--lpi", type=int, default=0, help="lanes per BP instance (0 = library choice)")
+    ap.add_argument("--wpb", type=int, default=4, help="waves per block (with --lpi)")
+    ap.add_argument("--chunk", type=int, default=8, help="shots per work item (with --lpi)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-shots", type=int, default=1500, help="oracle sample: shots per error rate")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -92,6 +96,17 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_bytes:
+        # Plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read for it
+        # calibrates the same counters on the BP kernel.
+        x = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_bytes=args.copy_bytes, dispatches=3)))
+        return
+
     import paper_2605_14170_amd as pk
     from workloads.configs import WORKLOADS
 
@@ -100,6 +115,9 @@ def main():
     shots = args.shots or wl.shots
     torch.cuda.set_device(0)
     dec, bx, bz = build_decoder(pk, wl, code, shots)
+    if args.lpi:
+        for form in (0, 1):
+            dec.set_config(form, args.lpi, args.wpb, args.chunk, 0)
     ps = list(wl.ps)
     stream = torch.cuda.current_stream()
 
@@ -157,7 +175,8 @@ def main():
                 dtype="f32", data="synthetic",
                 config=dict(workload=wl.key, code=code.name, n=code.n, L=wl.L, T=wl.T, alpha=wl.alpha,
                             ps=ps, shots_per_p=shots, schedule="flooding", rule="normalized min-sum",
-                            form=args.form, basis_mode=wl.basis_mode),
+                            form=args.form, basis_mode=wl.basis_mode,
+                            launch=dec.get_config(1 if args.form == "batched" else 0)),
                 edge_updates_per_s=edges / dt, per_p=per_p, roofline=roofline)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))

@@ -183,6 +183,20 @@ enum {
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
                      int64_t *counters, void *hip_stream);
 
+/* Launch configuration of the BP kernel (the autotuner's search space).
+ * form: 0 = mbbp_decode / mbbp_decode_detail, 1 = mbbp_decode_batched / mbbp_run.
+ * lanes_per_instance: 16, 32 or 64 (a wavefront holds 64 / lanes instances);
+ * waves_per_block >= 1 (reduced automatically to fit 64 KiB of LDS);
+ * chunk: shots per work item (64-lane kernel: decoded one after another by a wave);
+ * blocks: persistent grid size (form 1; 0 = 4 per compute unit).
+ * Every configuration gives bit-identical outputs.  MBBP_EUNSUPPORTED if the code
+ * does not fit the register tables of that lane count. */
+typedef struct {
+    int32_t lanes_per_instance, waves_per_block, chunk, blocks;
+} mbbp_launch_config;
+mbbp_status mbbp_set_config(mbbp_ctx *ctx, int32_t form, const mbbp_launch_config *cfg);
+mbbp_status mbbp_get_config(mbbp_ctx *ctx, int32_t form, mbbp_launch_config *cfg);
+
 /* Event timing of the BP kernel.  While enabled, every BP kernel launch of this
  * context is bracketed by HIP events recorded on the launch's stream.
  * mbbp_bp_time waits for those events and returns the summed elapsed time (ms)

@@ -240,6 +240,18 @@ class Decoder:
                                             _ptr(corr_z), _ptr(fail), _stream(stream)), "mbbp_failures")
         return fail
 
+    def set_config(self, form: int, lanes_per_instance: int, waves_per_block: int = 4, chunk: int = 8,
+                   blocks: int = 0) -> None:
+        """BP launch shape for form 0 (plain) or 1 (batched); outputs do not depend on it."""
+        cfg = _lib.LaunchConfig(int(lanes_per_instance), int(waves_per_block), int(chunk), int(blocks))
+        _lib.check(_lib.lib().mbbp_set_config(self._ctx, int(form), ctypes.byref(cfg)), "mbbp_set_config")
+
+    def get_config(self, form: int) -> dict:
+        cfg = _lib.LaunchConfig()
+        _lib.check(_lib.lib().mbbp_get_config(self._ctx, int(form), ctypes.byref(cfg)), "mbbp_get_config")
+        return dict(lanes_per_instance=cfg.lanes_per_instance, waves_per_block=cfg.waves_per_block,
+                    chunk=cfg.chunk, blocks=cfg.blocks)
+
     def set_timing(self, enable: bool) -> None:
         _lib.check(_lib.lib().mbbp_set_timing(self._ctx, 1 if enable else 0), "mbbp_set_timing")
 

@@ -39,6 +39,11 @@ class Bases(ctypes.Structure):
     _fields_ = [("hx", BasisList), ("hz", BasisList)]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("lanes_per_instance", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("rule", ctypes.c_int32), ("alpha", ctypes.c_float), ("r_max", ctypes.c_float),
                 ("select", ctypes.c_int32), ("max_batch", ctypes.c_int64), ("flags", ctypes.c_uint32)]
@@ -72,6 +77,8 @@ def lib() -> ctypes.CDLL:
             "mbbp_edge_counts": ([P, i32, P], i32),
             "mbbp_last_error": ([], ctypes.c_char_p),
             "mbbp_set_timing": ([P, i32], i32),
+            "mbbp_set_config": ([P, i32, ctypes.POINTER(LaunchConfig)], i32),
+            "mbbp_get_config": ([P, i32, ctypes.POINTER(LaunchConfig)], i32),
             "mbbp_bp_time": ([P, P, P, i32], i32),
         }
         for name, (args, res) in sig.items():
@@ -91,4 +98,4 @@ def check(status: int, where: str) -> None:
 EXPORTED = ["mbbp_params_default", "mbbp_create", "mbbp_destroy", "mbbp_decode", "mbbp_decode_batched",
             "mbbp_decode_detail", "mbbp_sample", "mbbp_failures", "mbbp_run", "mbbp_subtrees",
             "mbbp_build_bases", "mbbp_logicals", "mbbp_edge_counts", "mbbp_last_error", "mbbp_set_timing",
-            "mbbp_bp_time"]
+            "mbbp_bp_time", "mbbp_set_config", "mbbp_get_config"]

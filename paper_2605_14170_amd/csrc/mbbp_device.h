@@ -60,7 +60,9 @@ struct BPArgs {
     int64_t n_chunks;        // chunks per (part, l)
     unsigned long long *queue;
     int inst_bytes;          // LDS bytes per instance
-    int msg_bytes;           // MSG part of an instance (floats * 4)
+    int msg_bytes;           // message rows of an instance: (Mmax + 1) * 8 floats
+    int zero_bytes;          // message rows + decision rows (cleared at every fill), multiple of 16
+    int ws_max, w_max;       // syndrome words / candidate words of the launch's parts
 };
 
 struct SampleArgs {

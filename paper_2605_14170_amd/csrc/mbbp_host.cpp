@@ -436,16 +436,23 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
     return MBBP_OK;
 }
 
-int inst_bytes_for(const mbbp_ctx *c, int part0, int nparts, int *msg_bytes) {
-    int Mmax = 0, W = 0;
+// LDS layout of one BP instance (must match bp_kernel): (Mmax + 1) message rows of
+// 8 floats (the last is the sink row of absent edges), as many decision rows of 8
+// bytes, the syndrome words, the output staging words, and per-shot priors.
+void inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, mbbp::BPArgs &a) {
+    int Mmax = 0, W = 0, Ws = 0, n = 0;
     for (int p = part0; p < part0 + nparts; ++p) {
         Mmax = std::max(Mmax, c->dp[p].Mmax);
         W = std::max(W, c->dp[p].W);
+        Ws = std::max(Ws, c->dp[p].Ws);
+        n = std::max(n, c->dp[p].n);
     }
-    // (Mmax + 1) rows: the last is the sink row of absent edges
-    *msg_bytes = (Mmax + 1) * 32;
-    const int bytes = (Mmax + 1) * 32 + (Mmax + 1) * 8 + W * 8;
-    return (bytes + 15) & ~15;
+    a.msg_bytes = (Mmax + 1) * 32;
+    a.zero_bytes = (Mmax + 1) * 40;          // message + decision rows, a multiple of 8
+    a.ws_max = Ws;
+    a.w_max = W;
+    const int bytes = (Mmax + 1) * 40 + Ws * 8 + W * 8 + (per_shot_prior ? n * 4 : 0);
+    a.inst_bytes = (bytes + 15) & ~15;
 }
 
 mbbp_status ensure_run_workspace(mbbp_ctx *c) {
@@ -495,14 +502,16 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     const mbbp::BPConfig cfg = persistent ? c->batched_cfg : c->plain_cfg;
     const int G = 64 / cfg.lpi;
     a.persistent = persistent ? 1 : 0;
-    a.chunk = persistent ? cfg.chunk : G;
+    // plain form: an item is exactly one group of shots (G instances side by side, or
+    // `chunk` shots one after another for the 64-lane kernel)
+    a.chunk = persistent ? cfg.chunk : (cfg.lpi == 64 ? cfg.chunk : G);
     a.n_chunks = (shots + a.chunk - 1) / a.chunk;
     a.n_pl = nparts * c->dp[part0].L;
     a.n_items = a.n_chunks * a.n_pl;
     a.item_order = persistent ? c->item_order + (part0 == 1 ? 0 : 0) : nullptr;
     if (persistent && nparts != 2) a.item_order = nullptr;
     a.queue = c->w_queue;
-    a.inst_bytes = inst_bytes_for(c, part0, nparts, &a.msg_bytes);
+    inst_layout(c, part0, nparts, pps != 0, a);
     mbbp::BPConfig run = cfg;
     if (persistent) {
         run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
@@ -713,23 +722,16 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
             (void)lpi;
         }
         if (schedule != MBBP_FLOODING) return fail(MBBP_EUNSUPPORTED, "schedule not built yet");
-        // pick the plain configuration: widest instances that fit the register slots
-        int need16 = 0;
-        for (int p = 0; p < 2; ++p)
-            need16 = std::max({need16, (c->dp[p].n + 15) / 16, (c->dp[p].Mmax + 15) / 16});
-        int lpi = need16 <= 9 ? 16 : 0;
-        if (!lpi) {
-            int need32 = 0;
-            for (int p = 0; p < 2; ++p) need32 = std::max({need32, (c->dp[p].n + 31) / 32, (c->dp[p].Mmax + 31) / 32});
-            lpi = need32 <= 9 ? 32 : 64;
-        }
+        // default launch shape: one instance per wavefront (measured fastest on MI355X;
+        // the autotuner may pick another)
+        const int lpi = 64;
         int need = 0;
         for (int p = 0; p < 2; ++p)
             need = std::max({need, (c->dp[p].n + lpi - 1) / lpi, (c->dp[p].Mmax + lpi - 1) / lpi});
         if (!mbbp::bp_supported(lpi, need, c->dp[0].uniform_dc, prm.rule, schedule))
             return fail(MBBP_EUNSUPPORTED, "code too large for the register tables");
-        c->plain_cfg = mbbp::BPConfig{lpi, 4, 0, 0};
-        c->batched_cfg = mbbp::BPConfig{lpi, 4, 8, c->cu_count * 4};
+        c->plain_cfg = mbbp::BPConfig{lpi, 4, 8, 0};
+        c->batched_cfg = mbbp::BPConfig{lpi, 4, 16, c->cu_count * 4};
         // workspace
         const int64_t B = prm.max_batch;
         for (int p = 0; p < 2; ++p) {
@@ -911,6 +913,40 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     a.kmax_shot = ctx->w_kmax;
     e = mbbp::launch_fail(a, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("failure launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+static bool config_fits(const mbbp_ctx *c, int lpi) {
+    int need = 0;
+    for (int p = 0; p < 2; ++p)
+        need = std::max({need, (c->dp[p].n + lpi - 1) / lpi, (c->dp[p].Mmax + lpi - 1) / lpi});
+    return mbbp::bp_supported(lpi, need, c->dp[0].uniform_dc, c->params.rule, c->schedule);
+}
+
+mbbp_status mbbp_set_config(mbbp_ctx *ctx, int32_t form, const mbbp_launch_config *cfg) {
+    if (!ctx || !cfg) return fail(MBBP_EINVAL, "null argument");
+    if (form != 0 && form != 1) return fail(MBBP_EINVAL, "form must be 0 (plain) or 1 (batched)");
+    const int lpi = cfg->lanes_per_instance;
+    if (lpi != 16 && lpi != 32 && lpi != 64) return fail(MBBP_EINVAL, "lanes_per_instance must be 16, 32 or 64");
+    if (cfg->waves_per_block < 1 || cfg->waves_per_block > 4)  // kernels are built for 256 threads
+        return fail(MBBP_EINVAL, "waves_per_block in [1, 4]");
+    if (cfg->chunk < 1 || cfg->chunk > (1 << 20)) return fail(MBBP_EINVAL, "chunk in [1, 2^20]");
+    if (cfg->blocks < 0) return fail(MBBP_EINVAL, "blocks < 0");
+    if (!config_fits(ctx, lpi)) return fail(MBBP_EUNSUPPORTED, "code too large for this lane count");
+    mbbp::BPConfig b{lpi, cfg->waves_per_block, cfg->chunk, cfg->blocks > 0 ? cfg->blocks : ctx->cu_count * 4};
+    if (form == 0) ctx->plain_cfg = b;
+    else ctx->batched_cfg = b;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_get_config(mbbp_ctx *ctx, int32_t form, mbbp_launch_config *cfg) {
+    if (!ctx || !cfg) return fail(MBBP_EINVAL, "null argument");
+    if (form != 0 && form != 1) return fail(MBBP_EINVAL, "form must be 0 (plain) or 1 (batched)");
+    const mbbp::BPConfig &b = form == 0 ? ctx->plain_cfg : ctx->batched_cfg;
+    cfg->lanes_per_instance = b.lpi;
+    cfg->waves_per_block = b.waves_per_block;
+    cfg->chunk = b.chunk;
+    cfg->blocks = b.blocks;
     return MBBP_OK;
 }
 

@@ -235,53 +235,55 @@ template <typename T>
 __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 ? v[0] : v[1]; }
 
 // Variable rule (eq. (2) and the posterior of Section II-B) for one variable with
-// at most D edges whose ids are packed 16-bit in vo (absent edges point at the
-// instance's sink row): P = mu + sum r and q_k = mu + sum_{k' != k} r_k',
-// accumulated in ascending check order (never P - r_k).  MIXED: the pass holds
-// variables of different degrees, so edges k >= deg read as 0.
-template <int D, bool MIXED>
+// at most dmx <= 8 edges (dmx wave-uniform, so the guards below are scalar
+// branches) whose ids are packed 16-bit in vo; absent edges point at the
+// instance's sink row and read as 0 (deg is the lane's own degree).
+// P = mu + sum r and q_k = mu + sum_{k' != k} r_k', accumulated in ascending
+// check order (never P - r_k).
 __device__ __forceinline__ void var_rule(float *msg, unsigned char *dece, const uint32_t (&vo)[4], int deg,
-                                         float mu, float &P, bool &dec) {
-    float r[D];
-    uint32_t e[D];
+                                         int dmx, float mu, float &P, bool &dec) {
+    float r[kMaxVarDegree];
+    uint32_t e[kMaxVarDegree];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        e[k] = (k & 1) ? (vo[k >> 1] >> 16) : (vo[k >> 1] & 0xffffu);
-        const float x = msg[e[k]];
-        r[k] = (MIXED && k >= deg) ? 0.0f : x;
+    for (int k = 0; k < kMaxVarDegree; ++k) {
+        r[k] = 0.0f;
+        e[k] = 0;
+        if (k < dmx) {
+            e[k] = (k & 1) ? (vo[k >> 1] >> 16) : (vo[k >> 1] & 0xffffu);
+            const float x = msg[e[k]];
+            r[k] = k < deg ? x : 0.0f;
+        }
     }
-    float q[D];
+    float q[kMaxVarDegree];
     float pre = mu;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        float acc = pre;
+    for (int k = 0; k < kMaxVarDegree; ++k) {
+        q[k] = 0.0f;
+        if (k < dmx) {
+            float acc = pre;
 #pragma unroll
-        for (int k2 = k + 1; k2 < D; ++k2) acc += r[k2];
-        q[k] = acc;
-        pre += r[k];
+            for (int k2 = k + 1; k2 < kMaxVarDegree; ++k2)
+                if (k2 < dmx) acc += r[k2];
+            q[k] = acc;
+            pre += r[k];
+        }
     }
     dec = pre < 0.0f;
     P = pre;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        msg[e[k]] = q[k];
-        dece[e[k]] = (unsigned char)dec;
+    for (int k = 0; k < kMaxVarDegree; ++k) {
+        if (k < dmx) {
+            msg[e[k]] = q[k];
+            dece[e[k]] = (unsigned char)dec;
+        }
     }
-}
-
-// dmin: smallest degree among the pass's valid variables (wave-uniform).  Masking is
-// needed whenever some valid variable has fewer than D edges.
-template <int D>
-__device__ __forceinline__ void var_dispatch(int dmin, float *msg, unsigned char *dece, const uint32_t (&vo)[4],
-                                             int deg, float mu, float &P, bool &dec) {
-    if (dmin < D) var_rule<D, true>(msg, dece, vo, deg, mu, P, dec);
-    else var_rule<D, false>(msg, dece, vo, deg, mu, P, dec);
 }
 
 // DC: 6 = every row has weight 6 (no padding); 8 = rows of weight 2..8, unused slots
 // hold +FLT_MAX (never a minimum, neutral for box-plus) and decision byte 0.
 // Instance layout in LDS: (Mmax + 1) rows of 8 floats (row Mmax_part is the sink of
-// absent edges), the same rows of 8 decision bytes, then the staging words.
+// absent edges), the same rows of 8 decision bytes, the shot's syndrome words, the
+// staging words of the output, and (per-shot priors only) the shot's n priors.
 template <int LPI, int P, int DC, int RULE>
 __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
     constexpr int G = 64 / LPI;
@@ -295,7 +297,9 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
     unsigned char *wbase = smem + (size_t)wib * G * a.inst_bytes;
     float *msg = reinterpret_cast<float *>(wbase + g * a.inst_bytes);
     unsigned char *dece = wbase + g * a.inst_bytes + a.msg_bytes;
-    uint32_t *stage = reinterpret_cast<uint32_t *>(dece + a.msg_bytes / 4);
+    uint64_t *synl = reinterpret_cast<uint64_t *>(dece + a.msg_bytes / 4);
+    uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
+    float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
 
     // decision bytes (and the unused row slots) start at zero
     {
@@ -321,7 +325,6 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
     uint32_t voff[P][4];
     uint32_t vinfo[P];   // variable id | degree << 16
     int dmaxp[P];        // max degree over the valid slots of pass v (wave-uniform)
-    int dminp[P];        // min degree over the valid slots of pass v (wave-uniform)
     uint32_t cwp[P];     // row weights (DC == 8 only)
     float mu[P];
 
@@ -356,23 +359,14 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                 voff[v][0] = o.x; voff[v][1] = o.y; voff[v][2] = o.z; voff[v][3] = o.w;
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(valid ? deg : 0));
-                dminp[v] = uniform_i32(wave_min_i32(valid ? deg : kMaxVarDegree));
                 if (DC == 8) {
                     const int j = v * LPI + lig;
-                    cwp[v] = (v < cp && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 0u;
+                    cwp[v] = (v < cp && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
                 }
-            }
-            if (DC == 8) {
-                // unused row slots of every instance region: +FLT_MAX, decision 0
-                for (int gg = 0; gg < G; ++gg) {
-                    float *mg = reinterpret_cast<float *>(wbase + gg * a.inst_bytes);
-                    unsigned char *dg = wbase + gg * a.inst_bytes + a.msg_bytes;
-                    for (int i = lane; i < Mmax * 8; i += 64) {
-                        mg[i] = 3.402823466e38f;
-                        dg[i] = 0;
-                    }
+                if (!a.prior_per_shot) {
+                    const float *pr0 = pick(a.prior, ip.part);
+                    mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
                 }
-                wave_sync();
             }
         }
         const float *prior = pick(a.prior, ip.part);
@@ -397,23 +391,29 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                     asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
                                  "+v"(vinfo[v]));
                 if (need_fill) {
-                    // priors of this shot's variables, syndrome bits of this lane's checks,
-                    // and every check->variable message of the instance set to 0
-                    const float *pr = prior + (a.prior_per_shot ? shot * n : 0);
-#pragma unroll
-                    for (int v = 0; v < P; ++v) {
-                        const int s = v * LPI + lig;
-                        mu[v] = (v < vp && s < n) ? pr[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
-                        if (v < vp) {
-#pragma unroll
-                            for (int k = 0; k < kMaxVarDegree; ++k)
-                                if (k < uniform_i32(dmaxp[v])) {
-                                    const uint32_t e = (k & 1) ? (voff[v][k >> 1] >> 16) : (voff[v][k >> 1] & 0xffffu);
-                                    msg[e] = 0.0f;
-                                }
-                        }
+                    // zero every message and decision byte of the instance, stage the
+                    // shot's syndrome words (and priors) in LDS with coalesced loads
+                    {
+                        uint2 *z = reinterpret_cast<uint2 *>(msg);
+                        const int nz = a.zero_bytes / 8;
+                        for (int i = lig; i < nz; i += LPI) z[i] = make_uint2(0u, 0u);
                     }
                     const uint64_t *sy = syn + shot * Ws;
+                    if (lig < Ws) synl[lig] = sy[lig];
+                    if (a.prior_per_shot) {
+                        const float *pr = prior + shot * n;
+                        for (int i = lig; i < n; i += LPI) mul[i] = pr[i];
+                    }
+                }
+                wave_sync();
+                if (need_fill) {
+                    if (a.prior_per_shot) {
+#pragma unroll
+                        for (int v = 0; v < P; ++v) {
+                            const int s = v * LPI + lig;
+                            mu[v] = (v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
+                        }
+                    }
                     uint32_t sb = 0;
 #pragma unroll
                     for (int c = 0; c < P; ++c) {
@@ -422,11 +422,11 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                             const int src = j < m ? j : csrc[j];
                             uint32_t bit = 0;
                             if (src >= 0) {
-                                bit = (uint32_t)(sy[src >> 6] >> (src & 63)) & 1u;
+                                bit = (uint32_t)(synl[src >> 6] >> (src & 63)) & 1u;
                             } else {
                                 for (int t = pt->comb_ptr[-src - 1]; t < pt->comb_ptr[-src]; ++t) {
                                     const int r = pt->comb_idx[t];
-                                    bit ^= (uint32_t)(sy[r >> 6] >> (r & 63)) & 1u;
+                                    bit ^= (uint32_t)(synl[r >> 6] >> (r & 63)) & 1u;
                                 }
                             }
                             sb |= bit << c;
@@ -453,18 +453,9 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                 if (v < vp) {
                     const int deg = (int)(vinfo[v] >> 16);
                     const int dmx = uniform_i32(dmaxp[v]);
-                    const int dmn = uniform_i32(dminp[v]);
                     float Pv = 0.0f;
                     bool d = false;
-                    switch (dmx) {
-                    case 1: case 2: var_dispatch<2>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 3: var_dispatch<3>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 4: var_dispatch<4>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 5: var_dispatch<5>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 6: var_dispatch<6>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    case 7: case 8: var_dispatch<8>(dmn, msg, dece, voff[v], deg, mu[v], Pv, d); break;
-                    default: Pv = mu[v]; d = Pv < 0.0f; break;
-                    }
+                    var_rule(msg, dece, voff[v], deg, dmx, mu[v], Pv, d);
                     decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
                     if (llr) {
                         const int s = v * LPI + lig;
@@ -497,16 +488,16 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                     } else {
                         const float4 q1 = *reinterpret_cast<const float4 *>(row + 4);
                         q[4] = q1.x; q[5] = q1.y; q[6] = q1.z; q[7] = q1.w;
+                        const int w = (int)cwp[c];
+#pragma unroll
+                        for (int k = 2; k < DC; ++k)
+                            if (k >= w) q[k] = 3.402823466e38f;
                     }
                     CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
                     if constexpr (DC == 6) {
                         *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
                         *reinterpret_cast<float2 *>(row + 4) = make_float2(q[4], q[5]);
                     } else {
-                        const int w = (int)cwp[c];
-#pragma unroll
-                        for (int k = 2; k < DC; ++k)
-                            if (k >= w) q[k] = 3.402823466e38f;
                         *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
                         *reinterpret_cast<float4 *>(row + 4) = make_float4(q[4], q[5], q[6], q[7]);
                     }
@@ -566,6 +557,223 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
                     }
                 }
             }
+        }
+
+        if (a.persistent) {
+            unsigned long long v = 0;
+            if (lane == 0) v = atomicAdd(a.queue, 1ull);
+            item = uniform_i64((long long)v);
+        } else {
+            item = a.n_items;
+        }
+    }
+}
+
+// One instance per wavefront (the 64-lane case).  Every per-instance quantity (shot,
+// iteration, halting) is wave-uniform and lives in scalar registers; only the
+// per-lane edge tables, priors and syndrome bits are vector registers.  Shots of
+// a work item are decoded one after the other by the same wave.
+template <int P, int DC, int RULE>
+__global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *ibase = smem + (size_t)wib * a.inst_bytes;
+    float *msg = reinterpret_cast<float *>(ibase);
+    unsigned char *dece = ibase + a.msg_bytes;
+    uint64_t *synl = reinterpret_cast<uint64_t *>(dece + a.msg_bytes / 4);
+    uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
+    float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
+
+    int64_t item;
+    if (a.persistent) {
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(a.queue, 1ull);
+        item = uniform_i64((long long)v);
+    } else {
+        item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    }
+    const float alpha = a.alpha, rmax = a.rmax;
+    const int T = a.T;
+    int cur_key = -1;
+
+    uint32_t voff[P][4];
+    uint32_t vinfo[P];   // variable id | degree << 16
+    int dmaxp[P];        // max degree of pass v (wave-uniform)
+    uint32_t cwp[P];     // row weights (DC == 8 only)
+    float mu[P];
+
+    while (item < a.n_items) {
+        const ItemPos ip = decode_item(a, item);
+        const DevPart *pt = a.dparts + ip.part;
+        const int n = pt->n, m = pt->m, Mmax = pt->Mmax, W = pt->W, Ws = pt->Ws, L = pt->L;
+        const int l = ip.l;
+        const int Ml = pt->M[l];
+        const int vp = (n + 63) >> 6;
+        const int cp = (Ml + 63) >> 6;
+        const uint32_t sink = (uint32_t)Mmax * 8u;
+        const int key = ip.part * 256 + l;
+        if (key != cur_key) {
+            cur_key = key;
+            const uint4 *vo4 = reinterpret_cast<const uint4 *>(pt->voff) + (size_t)l * n;
+            const uint16_t *vid = pt->vid + (size_t)l * n;
+            const uint8_t *vdg = pt->vdeg + (size_t)l * n;
+            const float *pr0 = pick(a.prior, ip.part);
+#pragma unroll
+            for (int v = 0; v < P; ++v) {
+                const int s = v * 64 + lane;
+                const bool valid = v < vp && s < n;
+                const uint32_t sk2 = sink | (sink << 16);
+                uint4 o = make_uint4(sk2, sk2, sk2, sk2);
+                int deg = 0;
+                uint32_t id = 0;
+                if (valid) {
+                    o = vo4[s];
+                    deg = vdg[s];
+                    id = vid[s];
+                }
+                voff[v][0] = o.x; voff[v][1] = o.y; voff[v][2] = o.z; voff[v][3] = o.w;
+                vinfo[v] = id | ((uint32_t)deg << 16);
+                dmaxp[v] = uniform_i32(wave_max_i32(deg));
+                if (DC == 8) {
+                    const int j = v * 64 + lane;
+                    cwp[v] = (v < cp && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
+                }
+                if (!a.prior_per_shot) mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
+            }
+        }
+        const float *prior = pick(a.prior, ip.part);
+        const uint64_t *syn = pick(a.syn, ip.part);
+        uint64_t *cand = pick(a.cand, ip.part);
+        uint16_t *kstat = pick(a.kstat, ip.part);
+        float *llr = pick(a.llr, ip.part);
+        const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
+
+        for (int64_t shot = ip.begin; shot < ip.end; ++shot) {
+            // ---------------- fill: clear messages and decisions, stage syndrome (and priors)
+            {
+                uint4 *z = reinterpret_cast<uint4 *>(msg);
+                const int nz = a.zero_bytes / 16;
+                for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+                if (lane < Ws) synl[lane] = syn[shot * Ws + lane];
+                if (a.prior_per_shot) {
+                    const float *pr = prior + shot * n;
+                    for (int i = lane; i < n; i += 64) mul[i] = pr[i];
+                }
+            }
+            wave_sync();
+            if (a.prior_per_shot) {
+#pragma unroll
+                for (int v = 0; v < P; ++v) {
+                    const int s = v * 64 + lane;
+                    mu[v] = (v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
+                }
+            }
+            uint32_t sbits = 0;
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                const int j = c * 64 + lane;
+                if (c < cp && j < Ml) {
+                    const int src = j < m ? j : csrc[j];
+                    uint32_t bit = 0;
+                    if (src >= 0) {
+                        bit = (uint32_t)(synl[src >> 6] >> (src & 63)) & 1u;
+                    } else {
+                        for (int t = pt->comb_ptr[-src - 1]; t < pt->comb_ptr[-src]; ++t) {
+                            const int r = pt->comb_idx[t];
+                            bit ^= (uint32_t)(synl[r >> 6] >> (r & 63)) & 1u;
+                        }
+                    }
+                    sbits |= bit << c;
+                }
+            }
+            int it = 0, kfix = -1, K = T;
+            bool conv = false;
+            uint32_t decb = 0;
+            while (true) {
+#pragma unroll
+                for (int v = 0; v < P; ++v)
+                    asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
+                                 "+v"(vinfo[v]));
+                // ---------------- variable phase
+#pragma unroll
+                for (int v = 0; v < P; ++v) {
+                    if (v < vp) {
+                        const int deg = (int)(vinfo[v] >> 16);
+                        const int dmx = uniform_i32(dmaxp[v]);
+                        float Pv = 0.0f;
+                        bool d = false;
+                        var_rule(msg, dece, voff[v], deg, dmx, mu[v], Pv, d);
+                        decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
+                        if (llr) {
+                            const int s = v * 64 + lane;
+                            if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
+                        }
+                    }
+                }
+                wave_sync();
+                // ---------------- check phase
+                uint32_t unsat = 0;
+#pragma unroll
+                for (int c = 0; c < P; ++c) {
+                    if (c < cp) {
+                        const int jr = c * 64 + lane;
+                        const int j = jr < Ml ? jr : Mmax;
+                        float *row = msg + j * 8;
+                        const uint2 dd = *reinterpret_cast<const uint2 *>(dece + j * 8);
+                        const uint32_t sb = (sbits >> c) & 1u;
+                        unsat |= ((__popc(dd.x) + __popc(dd.y) + sb) & 1u) & (jr < Ml ? 1u : 0u);
+                        float q[DC];
+                        const float4 q0 = *reinterpret_cast<const float4 *>(row);
+                        q[0] = q0.x; q[1] = q0.y; q[2] = q0.z; q[3] = q0.w;
+                        if constexpr (DC == 6) {
+                            const float2 q1 = *reinterpret_cast<const float2 *>(row + 4);
+                            q[4] = q1.x; q[5] = q1.y;
+                        } else {
+                            const float4 q1 = *reinterpret_cast<const float4 *>(row + 4);
+                            q[4] = q1.x; q[5] = q1.y; q[6] = q1.z; q[7] = q1.w;
+                            const int w = (int)cwp[c];
+#pragma unroll
+                            for (int k = 2; k < DC; ++k)
+                                if (k >= w) q[k] = 3.402823466e38f;
+                        }
+                        CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
+                        *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
+                        if constexpr (DC == 6) {
+                            *reinterpret_cast<float2 *>(row + 4) = make_float2(q[4], q[5]);
+                        } else {
+                            *reinterpret_cast<float4 *>(row + 4) = make_float4(q[4], q[5], q[6], q[7]);
+                        }
+                    }
+                }
+                const bool sat = __ballot(unsat != 0u) == 0ull;
+                // ---------------- halting (Section II-B)
+                if (!a.fixed_T) {
+                    if (sat) { conv = true; K = it; break; }
+                    if (it == T) { K = T; break; }
+                } else {
+                    if (sat && kfix < 0) kfix = it;
+                    if (it == T) { conv = kfix >= 0; K = conv ? kfix : T; break; }
+                }
+                ++it;
+                wave_sync();
+            }
+            // ---------------- output: bit-packed hard decisions via the staging words
+            if (lane < 2 * W) stage[lane] = 0u;
+            wave_sync();
+#pragma unroll
+            for (int v = 0; v < P; ++v) {
+                const int s = v * 64 + lane;
+                if (v < vp && s < n && ((decb >> v) & 1u)) {
+                    const uint32_t id = vinfo[v] & 0xffffu;
+                    atomicOr(&stage[id >> 5], 1u << (id & 31));
+                }
+            }
+            wave_sync();
+            const size_t inst = (size_t)shot * L + l;
+            if (lane < W) cand[inst * W + lane] = reinterpret_cast<const uint64_t *>(stage)[lane];
+            if (lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
+            wave_sync();
         }
 
         if (a.persistent) {
@@ -814,8 +1022,23 @@ static hipError_t launch_bp_t(const BPArgs &a, const BPConfig &cfg, hipStream_t 
     return hipGetLastError();
 }
 
+template <int P, int DC, int RULE>
+static hipError_t launch_wave_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
+    const int wpb = cfg.waves_per_block;
+    const size_t lds = (size_t)wpb * a.inst_bytes;
+    const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
+    hipLaunchKernelGGL((bp_wave_kernel<P, DC, RULE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a);
+    return hipGetLastError();
+}
+
 template <int LPI, int P>
 static hipError_t launch_bp_p(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
+    if constexpr (LPI == 64) {
+        bool u6 = true;
+        for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
+        if (rule == 0) return u6 ? launch_wave_t<P, 6, 0>(a, cfg, s) : launch_wave_t<P, 8, 0>(a, cfg, s);
+        return u6 ? launch_wave_t<P, 6, 1>(a, cfg, s) : launch_wave_t<P, 8, 1>(a, cfg, s);
+    }
     bool u6 = true;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
     if (rule == 0) return u6 ? launch_bp_t<LPI, P, 6, 0>(a, cfg, s) : launch_bp_t<LPI, P, 8, 0>(a, cfg, s);

@@ -335,3 +335,35 @@ def test_nms_small_codes_padded_rows_bit_exact(pk, factory):
         np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
         np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
     dec.close()
+
+
+@pytest.mark.parametrize("key,p", [("bb144_L16_T50", 0.07), ("bb72_L4_T20", 0.06)])
+def test_launch_configs_bit_identical(pk, key, p):
+    """Every launch shape (lanes per instance, waves per block, shots per item, plain
+    or persistent) gives the same bits; the reference is the FP32 oracle."""
+    wl = WORKLOADS[key]
+    code = wl.code()
+    shots = 999
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
+    ex, ez, sx, sz = dec.sample(11, p, 3, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    ref = {}
+    for part, h, (bp, rows), syn, tag in ((0, code.hz, bz, sx, "x"), (1, code.hx, bx, sz, "z")):
+        r = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), wl.T, alpha=wl.alpha, precision="f32")
+        ref[tag] = r
+    for lpi in (16, 32, 64):
+        for wpb, chunk in ((1, 1), (4, 7), (2, 64)):
+            for form in (0, 1):
+                try:
+                    dec.set_config(form, lpi, wpb, chunk, 37 if form else 0)
+                except pk.MbbpError as e:
+                    assert e.status == -5
+                    continue
+                say(f"  {key} lpi={lpi} wpb={wpb} chunk={chunk} form={form}")
+                out = (dec.decode if form == 0 else dec.decode_batched)(sx, sz, prior, prior)
+                torch.cuda.synchronize()
+                for tag in ("x", "z"):
+                    np.testing.assert_array_equal(words(out[f"corr_{tag}"]), ref[tag].corr)
+                    np.testing.assert_array_equal(out[f"basis_{tag}"].cpu().numpy(), ref[tag].chosen)
+    dec.close()
