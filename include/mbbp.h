@@ -185,7 +185,7 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
 
 /* Launch configuration of the BP kernel (the autotuner's search space).
  * form: 0 = mbbp_decode / mbbp_decode_detail, 1 = mbbp_decode_batched / mbbp_run.
- * lanes_per_instance: 16, 32 or 64 (a wavefront holds 64 / lanes instances);
+ * lanes_per_instance: 64 (one instance per wavefront; other values: MBBP_EUNSUPPORTED);
  * waves_per_block >= 1 (reduced automatically to fit 64 KiB of LDS);
  * chunk: shots per work item (64-lane kernel: decoded one after another by a wave);
  * blocks: persistent grid size (form 1; 0 = 4 per compute unit).

@@ -118,6 +118,8 @@ hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncount
 hipError_t launch_run_prep(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
                            unsigned long long *queue, hipStream_t s);
 int bp_max_passes(int lpi);  // register slots available per lane for this lpi
+// Rows per instance (Mpad = 64 * check passes) of the kernel a launch would use; false if none fits.
+bool bp_layout(const BPArgs &a, int &mpad);
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();
 

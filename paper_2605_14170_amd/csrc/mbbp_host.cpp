@@ -436,23 +436,25 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
     return MBBP_OK;
 }
 
-// LDS layout of one BP instance (must match bp_kernel): (Mmax + 1) message rows of
-// 8 floats (the last is the sink row of absent edges), as many decision rows of 8
-// bytes, the syndrome words, the output staging words, and per-shot priors.
-void inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, mbbp::BPArgs &a) {
-    int Mmax = 0, W = 0, Ws = 0, n = 0;
+// LDS bytes of one BP instance (must match bp_wave_kernel): messages and decision
+// cells for Mpad rows of 8 slots (64 * Mpad bytes), the syndrome words, the output
+// staging words and, for per-shot priors, the shot's n priors.
+bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, mbbp::BPArgs &a) {
+    int W = 0, Ws = 0, n = 0;
     for (int p = part0; p < part0 + nparts; ++p) {
-        Mmax = std::max(Mmax, c->dp[p].Mmax);
         W = std::max(W, c->dp[p].W);
         Ws = std::max(Ws, c->dp[p].Ws);
         n = std::max(n, c->dp[p].n);
     }
-    a.msg_bytes = (Mmax + 1) * 32;
-    a.zero_bytes = (Mmax + 1) * 40;          // message + decision rows, a multiple of 8
+    int mpad = 0;
+    if (!mbbp::bp_layout(a, mpad)) return false;
     a.ws_max = Ws;
     a.w_max = W;
-    const int bytes = (Mmax + 1) * 40 + Ws * 8 + W * 8 + (per_shot_prior ? n * 4 : 0);
+    a.msg_bytes = 32 * mpad;
+    a.zero_bytes = 64 * mpad;
+    const int bytes = 64 * mpad + Ws * 8 + W * 8 + (per_shot_prior ? n * 4 : 0);
     a.inst_bytes = (bytes + 15) & ~15;
+    return true;
 }
 
 mbbp_status ensure_run_workspace(mbbp_ctx *c) {
@@ -500,18 +502,17 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         a.llr[p] = llr[p];
     }
     const mbbp::BPConfig cfg = persistent ? c->batched_cfg : c->plain_cfg;
-    const int G = 64 / cfg.lpi;
+    const int G = 1;  // one instance per wavefront
     a.persistent = persistent ? 1 : 0;
-    // plain form: an item is exactly one group of shots (G instances side by side, or
-    // `chunk` shots one after another for the 64-lane kernel)
-    a.chunk = persistent ? cfg.chunk : (cfg.lpi == 64 ? cfg.chunk : G);
+    a.chunk = cfg.chunk;  // shots of a work item, decoded one after another by a wave
     a.n_chunks = (shots + a.chunk - 1) / a.chunk;
     a.n_pl = nparts * c->dp[part0].L;
     a.n_items = a.n_chunks * a.n_pl;
     a.item_order = persistent ? c->item_order + (part0 == 1 ? 0 : 0) : nullptr;
     if (persistent && nparts != 2) a.item_order = nullptr;
     a.queue = c->w_queue;
-    inst_layout(c, part0, nparts, pps != 0, a);
+    if (!inst_layout(c, part0, nparts, pps != 0, a))
+        return fail(MBBP_EUNSUPPORTED, "code too large for the BP kernel's register tables");
     mbbp::BPConfig run = cfg;
     if (persistent) {
         run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
@@ -927,7 +928,7 @@ mbbp_status mbbp_set_config(mbbp_ctx *ctx, int32_t form, const mbbp_launch_confi
     if (!ctx || !cfg) return fail(MBBP_EINVAL, "null argument");
     if (form != 0 && form != 1) return fail(MBBP_EINVAL, "form must be 0 (plain) or 1 (batched)");
     const int lpi = cfg->lanes_per_instance;
-    if (lpi != 16 && lpi != 32 && lpi != 64) return fail(MBBP_EINVAL, "lanes_per_instance must be 16, 32 or 64");
+    if (lpi != 64) return fail(MBBP_EUNSUPPORTED, "lanes_per_instance: only 64 (one instance per wavefront) is built");
     if (cfg->waves_per_block < 1 || cfg->waves_per_block > 4)  // kernels are built for 256 threads
         return fail(MBBP_EINVAL, "waves_per_block in [1, 4]");
     if (cfg->chunk < 1 || cfg->chunk > (1 << 20)) return fail(MBBP_EINVAL, "chunk in [1, 2^20]");

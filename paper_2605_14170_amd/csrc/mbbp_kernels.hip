@@ -234,354 +234,75 @@ __device__ __forceinline__ ItemPos decode_item(const BPArgs &a, int64_t item) {
 template <typename T>
 __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 ? v[0] : v[1]; }
 
-// Variable rule (eq. (2) and the posterior of Section II-B) for one variable with
-// at most dmx <= 8 edges (dmx wave-uniform, so the guards below are scalar
-// branches) whose ids are packed 16-bit in vo; absent edges point at the
-// instance's sink row and read as 0 (deg is the lane's own degree).
-// P = mu + sum r and q_k = mu + sum_{k' != k} r_k', accumulated in ascending
-// check order (never P - r_k).
-__device__ __forceinline__ void var_rule(float *msg, unsigned char *dece, const uint32_t (&vo)[4], int deg,
-                                         int dmx, float mu, float &P, bool &dec) {
-    float r[kMaxVarDegree];
-    uint32_t e[kMaxVarDegree];
+typedef __attribute__((address_space(3))) float lds_f32;
+typedef __attribute__((address_space(3))) unsigned char lds_u8;
+
+__device__ __forceinline__ lds_f32 *lds_ptr_f32(uint32_t byte_addr) { return (lds_f32 *)(size_t)byte_addr; }
+__device__ __forceinline__ lds_u8 *lds_ptr_u8(uint32_t byte_addr) { return (lds_u8 *)(size_t)byte_addr; }
+
+// LDS layout of one BP instance, 64 * PC rows (Mpad) of at most 8 edge slots:
+//   messages  float [8][Mpad]  slot-major: edge (j, k) at k * Mpad + j
+//   decisions u8    [8][Mpad]  stored as 32-bit cells at the message offset + 32 * Mpad,
+//                              so one table address serves both arrays
+//   syndrome words, output staging words, per-shot priors.
+// Rows >= M_l are unused by representation l; row Mmax (of the part) is the sink
+// of absent edges.  Every table entry is a byte address in LDS.
+template <int PC>
+struct Layout {
+    static constexpr int Mpad = 64 * PC;
+    static constexpr uint32_t kDecOff = 32u * Mpad;       // decisions after the messages
+    static constexpr uint32_t kTail = 64u * Mpad;         // syndrome words start here
+};
+
+// Variable rule (eq. (2) and the posterior of Section II-B) for a variable of
+// degree deg <= D (edges k >= deg point at the sink and read as 0):
+// P = mu + sum r,  q_k = mu + sum_{k' != k} r_k'  accumulated in ascending check
+// order (never P - r_k); every q_k and the hard decision are written back.
+template <int D, uint32_t DECOFF>
+__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
+    float r[D];
 #pragma unroll
-    for (int k = 0; k < kMaxVarDegree; ++k) {
-        r[k] = 0.0f;
-        e[k] = 0;
-        if (k < dmx) {
-            e[k] = (k & 1) ? (vo[k >> 1] >> 16) : (vo[k >> 1] & 0xffffu);
-            const float x = msg[e[k]];
-            r[k] = k < deg ? x : 0.0f;
-        }
+    for (int k = 0; k < D; ++k) {
+        const float x = *lds_ptr_f32(ea[k]);
+        r[k] = k < deg ? x : 0.0f;
     }
-    float q[kMaxVarDegree];
+    float q[D];
     float pre = mu;
 #pragma unroll
-    for (int k = 0; k < kMaxVarDegree; ++k) {
-        q[k] = 0.0f;
-        if (k < dmx) {
-            float acc = pre;
+    for (int k = 0; k < D; ++k) {
+        float acc = pre;
 #pragma unroll
-            for (int k2 = k + 1; k2 < kMaxVarDegree; ++k2)
-                if (k2 < dmx) acc += r[k2];
-            q[k] = acc;
-            pre += r[k];
-        }
+        for (int k2 = k + 1; k2 < D; ++k2) acc += r[k2];
+        q[k] = acc;
+        pre += r[k];
     }
     dec = pre < 0.0f;
     P = pre;
 #pragma unroll
-    for (int k = 0; k < kMaxVarDegree; ++k) {
-        if (k < dmx) {
-            msg[e[k]] = q[k];
-            dece[e[k]] = (unsigned char)dec;
-        }
+    for (int k = 0; k < D; ++k) {
+        *lds_ptr_f32(ea[k]) = q[k];
+        *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
     }
 }
 
-// DC: 6 = every row has weight 6 (no padding); 8 = rows of weight 2..8, unused slots
-// hold +FLT_MAX (never a minimum, neutral for box-plus) and decision byte 0.
-// Instance layout in LDS: (Mmax + 1) rows of 8 floats (row Mmax_part is the sink of
-// absent edges), the same rows of 8 decision bytes, the shot's syndrome words, the
-// staging words of the output, and (per-shot priors only) the shot's n priors.
-template <int LPI, int P, int DC, int RULE>
-__global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_kernel(BPArgs a) {
-    constexpr int G = 64 / LPI;
-    constexpr uint64_t GMASK = (LPI == 64) ? ~0ull : ((1ull << LPI) - 1ull);
-    const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
-    const int g = lane / LPI;
-    const int lig = lane - g * LPI;
-
-    extern __shared__ __align__(16) unsigned char smem[];
-    unsigned char *wbase = smem + (size_t)wib * G * a.inst_bytes;
-    float *msg = reinterpret_cast<float *>(wbase + g * a.inst_bytes);
-    unsigned char *dece = wbase + g * a.inst_bytes + a.msg_bytes;
-    uint64_t *synl = reinterpret_cast<uint64_t *>(dece + a.msg_bytes / 4);
-    uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
-    float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
-
-    // decision bytes (and the unused row slots) start at zero
-    {
-        uint32_t *w32 = reinterpret_cast<uint32_t *>(wbase);
-        const int nw = G * a.inst_bytes / 4;
-        for (int i = lane; i < nw; i += 64) w32[i] = 0u;
-    }
-    wave_sync();
-
-    int64_t item;
-    if (a.persistent) {
-        unsigned long long v = 0;
-        if (lane == 0) v = atomicAdd(a.queue, 1ull);
-        item = uniform_i64((long long)v);
-    } else {
-        item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
-    }
-    const float alpha = a.alpha, rmax = a.rmax;
-    const int T = a.T;
-    int cur_key = -1;
-
-    // per-lane tables of the current representation (VGPRs)
-    uint32_t voff[P][4];
-    uint32_t vinfo[P];   // variable id | degree << 16
-    int dmaxp[P];        // max degree over the valid slots of pass v (wave-uniform)
-    uint32_t cwp[P];     // row weights (DC == 8 only)
-    float mu[P];
-
-    while (item < a.n_items) {
-        const ItemPos ip = decode_item(a, item);
-        const DevPart *pt = a.dparts + ip.part;
-        const int n = pt->n, m = pt->m, Mmax = pt->Mmax, W = pt->W, Ws = pt->Ws, L = pt->L;
-        const int l = ip.l;
-        const int Ml = pt->M[l];
-        const int vp = (n + LPI - 1) / LPI;
-        const int cp = (Ml + LPI - 1) / LPI;
-        const uint32_t sink = (uint32_t)Mmax * 8u;
-        const int key = ip.part * 256 + l;
-        if (key != cur_key) {
-            cur_key = key;
-            const uint4 *vo4 = reinterpret_cast<const uint4 *>(pt->voff) + (size_t)l * n;
-            const uint16_t *vid = pt->vid + (size_t)l * n;
-            const uint8_t *vdg = pt->vdeg + (size_t)l * n;
-#pragma unroll
-            for (int v = 0; v < P; ++v) {
-                const int s = v * LPI + lig;
-                const bool valid = v < vp && s < n;
-                const uint32_t sk2 = sink | (sink << 16);
-                uint4 o = make_uint4(sk2, sk2, sk2, sk2);
-                int deg = 0;
-                uint32_t id = 0;
-                if (valid) {
-                    o = vo4[s];
-                    deg = vdg[s];
-                    id = vid[s];
-                }
-                voff[v][0] = o.x; voff[v][1] = o.y; voff[v][2] = o.z; voff[v][3] = o.w;
-                vinfo[v] = id | ((uint32_t)deg << 16);
-                dmaxp[v] = uniform_i32(wave_max_i32(valid ? deg : 0));
-                if (DC == 8) {
-                    const int j = v * LPI + lig;
-                    cwp[v] = (v < cp && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
-                }
-                if (!a.prior_per_shot) {
-                    const float *pr0 = pick(a.prior, ip.part);
-                    mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
-                }
-            }
-        }
-        const float *prior = pick(a.prior, ip.part);
-        const uint64_t *syn = pick(a.syn, ip.part);
-        uint64_t *cand = pick(a.cand, ip.part);
-        uint16_t *kstat = pick(a.kstat, ip.part);
-        float *llr = pick(a.llr, ip.part);
-        const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
-
-        // per-instance state, identical in the LPI lanes of a group
-        int64_t shot = (ip.begin + g < ip.end) ? ip.begin + g : -1;
-        int64_t cn = min(ip.begin + G, ip.end);
-        const int64_t ce = ip.end;
-        bool need_fill = shot >= 0;
-        int it = 0, kfix = -1;
-        uint32_t sbits = 0, decb = 0;
-
-        while (true) {
-            if (__ballot(need_fill) != 0ull) {
-#pragma unroll
-                for (int v = 0; v < P; ++v)
-                    asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
-                                 "+v"(vinfo[v]));
-                if (need_fill) {
-                    // zero every message and decision byte of the instance, stage the
-                    // shot's syndrome words (and priors) in LDS with coalesced loads
-                    {
-                        uint2 *z = reinterpret_cast<uint2 *>(msg);
-                        const int nz = a.zero_bytes / 8;
-                        for (int i = lig; i < nz; i += LPI) z[i] = make_uint2(0u, 0u);
-                    }
-                    const uint64_t *sy = syn + shot * Ws;
-                    if (lig < Ws) synl[lig] = sy[lig];
-                    if (a.prior_per_shot) {
-                        const float *pr = prior + shot * n;
-                        for (int i = lig; i < n; i += LPI) mul[i] = pr[i];
-                    }
-                }
-                wave_sync();
-                if (need_fill) {
-                    if (a.prior_per_shot) {
-#pragma unroll
-                        for (int v = 0; v < P; ++v) {
-                            const int s = v * LPI + lig;
-                            mu[v] = (v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
-                        }
-                    }
-                    uint32_t sb = 0;
-#pragma unroll
-                    for (int c = 0; c < P; ++c) {
-                        const int j = c * LPI + lig;
-                        if (c < cp && j < Ml) {
-                            const int src = j < m ? j : csrc[j];
-                            uint32_t bit = 0;
-                            if (src >= 0) {
-                                bit = (uint32_t)(synl[src >> 6] >> (src & 63)) & 1u;
-                            } else {
-                                for (int t = pt->comb_ptr[-src - 1]; t < pt->comb_ptr[-src]; ++t) {
-                                    const int r = pt->comb_idx[t];
-                                    bit ^= (uint32_t)(synl[r >> 6] >> (r & 63)) & 1u;
-                                }
-                            }
-                            sb |= bit << c;
-                        }
-                    }
-                    sbits = sb;
-                    it = 0;
-                    kfix = -1;
-                    need_fill = false;
-                }
-            }
-            if (__ballot(shot >= 0) == 0ull) break;
-            const bool active = shot >= 0;
-            // Keep the packed edge tables opaque to loop-invariant code motion: unpacking
-            // them here costs one ALU op per edge, hoisting would cost 4x the VGPRs.
-#pragma unroll
-            for (int v = 0; v < P; ++v)
-                asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
-                             "+v"(vinfo[v]));
-
-            // ---------------- variable phase: posteriors, decisions, v->c exclusion sums
-#pragma unroll
-            for (int v = 0; v < P; ++v) {
-                if (v < vp) {
-                    const int deg = (int)(vinfo[v] >> 16);
-                    const int dmx = uniform_i32(dmaxp[v]);
-                    float Pv = 0.0f;
-                    bool d = false;
-                    var_rule(msg, dece, voff[v], deg, dmx, mu[v], Pv, d);
-                    decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                    if (llr) {
-                        const int s = v * LPI + lig;
-                        if (active && s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            wave_sync();
-
-            // ---------------- check phase: syndrome test of the decisions, c->v messages.
-            // Slots beyond the representation's checks work on the sink row (garbage in,
-            // garbage out) and do not count in the syndrome test.
-            uint32_t unsat = 0;
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                if (c < cp) {
-                    const int jr = c * LPI + lig;
-                    const int j = jr < Ml ? jr : Mmax;
-                    float *row = msg + j * 8;
-                    const uint2 dd = *reinterpret_cast<const uint2 *>(dece + j * 8);
-                    const uint32_t sb = (sbits >> c) & 1u;
-                    unsat |= ((__popc(dd.x) + __popc(dd.y) + sb) & 1u) & (jr < Ml ? 1u : 0u);
-                    float q[DC];
-                    const float4 q0 = *reinterpret_cast<const float4 *>(row);
-                    q[0] = q0.x; q[1] = q0.y; q[2] = q0.z; q[3] = q0.w;
-                    if constexpr (DC == 6) {
-                        const float2 q1 = *reinterpret_cast<const float2 *>(row + 4);
-                        q[4] = q1.x; q[5] = q1.y;
-                    } else {
-                        const float4 q1 = *reinterpret_cast<const float4 *>(row + 4);
-                        q[4] = q1.x; q[5] = q1.y; q[6] = q1.z; q[7] = q1.w;
-                        const int w = (int)cwp[c];
-#pragma unroll
-                        for (int k = 2; k < DC; ++k)
-                            if (k >= w) q[k] = 3.402823466e38f;
-                    }
-                    CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
-                    if constexpr (DC == 6) {
-                        *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
-                        *reinterpret_cast<float2 *>(row + 4) = make_float2(q[4], q[5]);
-                    } else {
-                        *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
-                        *reinterpret_cast<float4 *>(row + 4) = make_float4(q[4], q[5], q[6], q[7]);
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            const uint64_t um = __ballot(unsat != 0u);
-            const bool gunsat = ((um >> (g * LPI)) & GMASK) != 0ull;
-
-            // ---------------- halting (Section II-B): syndrome met, or the iteration cap
-            bool finish = false, conv = false;
-            int K = 0;
-            if (active) {
-                if (!a.fixed_T) {
-                    if (!gunsat) { finish = true; conv = true; K = it; }
-                    else if (it == T) { finish = true; conv = false; K = T; }
-                    else ++it;
-                } else {
-                    if (!gunsat && kfix < 0) kfix = it;
-                    if (it == T) { finish = true; conv = kfix >= 0; K = conv ? kfix : T; }
-                    else ++it;
-                }
-            }
-            wave_sync();
-            if (__ballot(finish) != 0ull) {
-                // hard decisions -> bit-packed candidate via the instance's staging words
-                if (finish && lig < 2 * W) stage[lig] = 0u;
-                wave_sync();
-                if (finish) {
-#pragma unroll
-                    for (int v = 0; v < P; ++v) {
-                        const int s = v * LPI + lig;
-                        if (v < vp && s < n && ((decb >> v) & 1u)) {
-                            const uint32_t id = vinfo[v] & 0xffffu;
-                            atomicOr(&stage[id >> 5], 1u << (id & 31));
-                        }
-                    }
-                }
-                wave_sync();
-                if (finish) {
-                    const size_t inst = (size_t)shot * L + l;
-                    if (lig < W) cand[inst * W + lig] = reinterpret_cast<const uint64_t *>(stage)[lig];
-                    if (lig == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
-                    shot = -1;
-                }
-                wave_sync();
-                // refill finished instances from the item's remaining shots, in group order
-                const uint64_t freem = __ballot(shot < 0 && lig == 0);
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) {
-                    if (((freem >> (gg * LPI)) & 1ull) && cn < ce) {
-                        if (g == gg) {
-                            shot = cn;
-                            need_fill = true;
-                        }
-                        ++cn;
-                    }
-                }
-            }
-        }
-
-        if (a.persistent) {
-            unsigned long long v = 0;
-            if (lane == 0) v = atomicAdd(a.queue, 1ull);
-            item = uniform_i64((long long)v);
-        } else {
-            item = a.n_items;
-        }
-    }
-}
-
-// One instance per wavefront (the 64-lane case).  Every per-instance quantity (shot,
-// iteration, halting) is wave-uniform and lives in scalar registers; only the
-// per-lane edge tables, priors and syndrome bits are vector registers.  Shots of
-// a work item are decoded one after the other by the same wave.
-template <int P, int DC, int RULE>
+// One instance per wavefront.  Every per-instance quantity (shot, iteration,
+// halting) is wave-uniform; per lane live only the variable slots' edge addresses,
+// priors and the check slots' syndrome bits.  Variable slots: s = v * 64 + lane,
+// v < PV (slots sorted by degree, so a pass has one degree almost everywhere);
+// checks: j = c * 64 + lane, c < PC.  The shots of a work item are decoded one
+// after another by the same wave.
+// DC: 6 = every row has weight 6; 8 = rows of weight 2..8 with unused slots read
+// as +FLT_MAX (never a minimum, neutral for box-plus).
+template <int PV, int PC, int DC, int RULE>
 __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
+    using LY = Layout<PC>;
+    constexpr int Mpad = LY::Mpad;
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *ibase = smem + (size_t)wib * a.inst_bytes;
-    float *msg = reinterpret_cast<float *>(ibase);
-    unsigned char *dece = ibase + a.msg_bytes;
-    uint64_t *synl = reinterpret_cast<uint64_t *>(dece + a.msg_bytes / 4);
+    const uint32_t ibase_addr = (uint32_t)(size_t)(lds_u8 *)ibase;
+    uint64_t *synl = reinterpret_cast<uint64_t *>(ibase + LY::kTail);
     uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
     float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
 
@@ -597,11 +318,11 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
     const int T = a.T;
     int cur_key = -1;
 
-    uint32_t voff[P][4];
-    uint32_t vinfo[P];   // variable id | degree << 16
-    int dmaxp[P];        // max degree of pass v (wave-uniform)
-    uint32_t cwp[P];     // row weights (DC == 8 only)
-    float mu[P];
+    uint32_t ea[PV][kMaxVarDegree];  // LDS byte address of every edge of the lane's variables
+    uint32_t vinfo[PV];              // variable id | degree << 16
+    int dmaxp[PV];                   // max degree of pass v (wave-uniform)
+    uint32_t cwp[PC];                // row weights (DC == 8 only)
+    float mu[PV];
 
     while (item < a.n_items) {
         const ItemPos ip = decode_item(a, item);
@@ -610,17 +331,17 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
         const int l = ip.l;
         const int Ml = pt->M[l];
         const int vp = (n + 63) >> 6;
-        const int cp = (Ml + 63) >> 6;
-        const uint32_t sink = (uint32_t)Mmax * 8u;
         const int key = ip.part * 256 + l;
         if (key != cur_key) {
             cur_key = key;
+            // edge ids e = j * 8 + k  ->  address of (j, k) in the slot-major layout
             const uint4 *vo4 = reinterpret_cast<const uint4 *>(pt->voff) + (size_t)l * n;
             const uint16_t *vid = pt->vid + (size_t)l * n;
             const uint8_t *vdg = pt->vdeg + (size_t)l * n;
             const float *pr0 = pick(a.prior, ip.part);
+            const uint32_t sink = (uint32_t)Mmax * 8u;
 #pragma unroll
-            for (int v = 0; v < P; ++v) {
+            for (int v = 0; v < PV; ++v) {
                 const int s = v * 64 + lane;
                 const bool valid = v < vp && s < n;
                 const uint32_t sk2 = sink | (sink << 16);
@@ -632,14 +353,22 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
                     deg = vdg[s];
                     id = vid[s];
                 }
-                voff[v][0] = o.x; voff[v][1] = o.y; voff[v][2] = o.z; voff[v][3] = o.w;
+                const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                for (int k = 0; k < kMaxVarDegree; ++k) {
+                    const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+                    ea[v][k] = ibase_addr + 4u * ((e & 7u) * (uint32_t)Mpad + (e >> 3));
+                }
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
-                if (DC == 8) {
-                    const int j = v * 64 + lane;
-                    cwp[v] = (v < cp && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
-                }
                 if (!a.prior_per_shot) mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
+            }
+            if (DC == 8) {
+#pragma unroll
+                for (int c = 0; c < PC; ++c) {
+                    const int j = c * 64 + lane;
+                    cwp[c] = j < Ml ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
+                }
             }
         }
         const float *prior = pick(a.prior, ip.part);
@@ -652,8 +381,8 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
         for (int64_t shot = ip.begin; shot < ip.end; ++shot) {
             // ---------------- fill: clear messages and decisions, stage syndrome (and priors)
             {
-                uint4 *z = reinterpret_cast<uint4 *>(msg);
-                const int nz = a.zero_bytes / 16;
+                uint4 *z = reinterpret_cast<uint4 *>(ibase);
+                constexpr int nz = (int)(LY::kTail / 16);
                 for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
                 if (lane < Ws) synl[lane] = syn[shot * Ws + lane];
                 if (a.prior_per_shot) {
@@ -664,16 +393,16 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
             wave_sync();
             if (a.prior_per_shot) {
 #pragma unroll
-                for (int v = 0; v < P; ++v) {
+                for (int v = 0; v < PV; ++v) {
                     const int s = v * 64 + lane;
                     mu[v] = (v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
                 }
             }
             uint32_t sbits = 0;
 #pragma unroll
-            for (int c = 0; c < P; ++c) {
+            for (int c = 0; c < PC; ++c) {
                 const int j = c * 64 + lane;
-                if (c < cp && j < Ml) {
+                if (j < Ml) {
                     const int src = j < m ? j : csrc[j];
                     uint32_t bit = 0;
                     if (src >= 0) {
@@ -691,19 +420,24 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
             bool conv = false;
             uint32_t decb = 0;
             while (true) {
-#pragma unroll
-                for (int v = 0; v < P; ++v)
-                    asm volatile("" : "+v"(voff[v][0]), "+v"(voff[v][1]), "+v"(voff[v][2]), "+v"(voff[v][3]),
-                                 "+v"(vinfo[v]));
                 // ---------------- variable phase
 #pragma unroll
-                for (int v = 0; v < P; ++v) {
+                for (int v = 0; v < PV; ++v) {
                     if (v < vp) {
                         const int deg = (int)(vinfo[v] >> 16);
-                        const int dmx = uniform_i32(dmaxp[v]);
                         float Pv = 0.0f;
                         bool d = false;
-                        var_rule(msg, dece, voff[v], deg, dmx, mu[v], Pv, d);
+                        switch (uniform_i32(dmaxp[v])) {
+                        case 1: var_rule<1, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 2: var_rule<2, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 3: var_rule<3, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 4: var_rule<4, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 5: var_rule<5, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 6: var_rule<6, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 7: var_rule<7, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        case 8: var_rule<8, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                        default: Pv = mu[v]; d = Pv < 0.0f; break;
+                        }
                         decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
                         if (llr) {
                             const int s = v * 64 + lane;
@@ -712,39 +446,31 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
                     }
                 }
                 wave_sync();
-                // ---------------- check phase
+                // ---------------- check phase: syndrome test of the decisions, c->v messages.
+                // Rows beyond the representation's checks are junk rows (unused by it).
                 uint32_t unsat = 0;
 #pragma unroll
-                for (int c = 0; c < P; ++c) {
-                    if (c < cp) {
-                        const int jr = c * 64 + lane;
-                        const int j = jr < Ml ? jr : Mmax;
-                        float *row = msg + j * 8;
-                        const uint2 dd = *reinterpret_cast<const uint2 *>(dece + j * 8);
-                        const uint32_t sb = (sbits >> c) & 1u;
-                        unsat |= ((__popc(dd.x) + __popc(dd.y) + sb) & 1u) & (jr < Ml ? 1u : 0u);
-                        float q[DC];
-                        const float4 q0 = *reinterpret_cast<const float4 *>(row);
-                        q[0] = q0.x; q[1] = q0.y; q[2] = q0.z; q[3] = q0.w;
-                        if constexpr (DC == 6) {
-                            const float2 q1 = *reinterpret_cast<const float2 *>(row + 4);
-                            q[4] = q1.x; q[5] = q1.y;
-                        } else {
-                            const float4 q1 = *reinterpret_cast<const float4 *>(row + 4);
-                            q[4] = q1.x; q[5] = q1.y; q[6] = q1.z; q[7] = q1.w;
-                            const int w = (int)cwp[c];
+                for (int c = 0; c < PC; ++c) {
+                    const int j = c * 64 + lane;
+                    lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+                    const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
+                    float q[DC];
+                    uint32_t par = (sbits >> c) & 1u;
 #pragma unroll
-                            for (int k = 2; k < DC; ++k)
-                                if (k >= w) q[k] = 3.402823466e38f;
-                        }
-                        CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
-                        *reinterpret_cast<float4 *>(row) = make_float4(q[0], q[1], q[2], q[3]);
-                        if constexpr (DC == 6) {
-                            *reinterpret_cast<float2 *>(row + 4) = make_float2(q[4], q[5]);
-                        } else {
-                            *reinterpret_cast<float4 *>(row + 4) = make_float4(q[4], q[5], q[6], q[7]);
-                        }
+                    for (int k = 0; k < DC; ++k) {
+                        q[k] = row[k * Mpad];
+                        par ^= drow[4 * k * Mpad];
                     }
+                    if constexpr (DC == 8) {
+                        const int w = (int)cwp[c];
+#pragma unroll
+                        for (int k = 2; k < DC; ++k)
+                            if (k >= w) q[k] = 3.402823466e38f;
+                    }
+                    unsat |= par & (j < Ml ? 1u : 0u);
+                    CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
+#pragma unroll
+                    for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
                 }
                 const bool sat = __ballot(unsat != 0u) == 0ull;
                 // ---------------- halting (Section II-B)
@@ -762,7 +488,7 @@ __global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
             if (lane < 2 * W) stage[lane] = 0u;
             wave_sync();
 #pragma unroll
-            for (int v = 0; v < P; ++v) {
+            for (int v = 0; v < PV; ++v) {
                 const int s = v * 64 + lane;
                 if (v < vp && s < n && ((decb >> v) & 1u)) {
                     const uint32_t id = vinfo[v] & 0xffffu;
@@ -979,92 +705,81 @@ hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncount
 
 size_t bp_lds_limit() { return 64 * 1024; }  // per workgroup
 
-// Instantiated (LPI, P) pairs: P = register slots per lane for checks and variables.
-static const int kP16[] = {3, 6, 9};
-static const int kP32[] = {3, 5, 9};
-static const int kP64[] = {2, 3, 5, 9, 14, 16};
+// Instantiated (PV, PC): variable and check passes of 64 lanes.
+struct PassPair {
+    int pv, pc;
+};
+static const PassPair kPairs[] = {{1, 1}, {2, 1}, {2, 2}, {3, 2}, {3, 3}, {5, 5}, {9, 9}, {14, 14}, {16, 16}};
 
-static int pick_passes(int lpi, int need) {
-    const int *lst = lpi == 16 ? kP16 : (lpi == 32 ? kP32 : kP64);
-    const int cnt = lpi == 64 ? 6 : 3;
-    for (int i = 0; i < cnt; ++i)
-        if (lst[i] >= need) return lst[i];
-    return -1;
+static bool pick_pair(int pv_need, int pc_need, PassPair &out) {
+    for (const PassPair &p : kPairs)
+        if (p.pv >= pv_need && p.pc >= pc_need) { out = p; return true; }
+    return false;
 }
 
-int bp_max_passes(int lpi) { return lpi == 64 ? 16 : 9; }
-
-static int passes_needed(const BPArgs &a, int lpi) {
-    int need = 1;
+static void passes_needed(const BPArgs &a, int &pv, int &pc) {
+    pv = 1; pc = 1;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) {
-        need = max(need, (a.part[p].n + lpi - 1) / lpi);
-        need = max(need, (a.part[p].Mmax + lpi - 1) / lpi);
+        pv = max(pv, (a.part[p].n + 63) / 64);
+        pc = max(pc, (a.part[p].Mmax + 1 + 63) / 64);  // + the sink row
     }
-    return need;
 }
+
+int bp_max_passes(int lpi) { return lpi == 64 ? 16 : 0; }
 
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule) {
     (void)dc_uniform;
-    if (schedule != 0) return false;
-    if (rule != 0 && rule != 1) return false;
-    if (lpi != 16 && lpi != 32 && lpi != 64) return false;
-    return pick_passes(lpi, passes) > 0;
+    if (schedule != 0 || (rule != 0 && rule != 1) || lpi != 64) return false;
+    PassPair pp;
+    return pick_pair(passes, passes, pp);
 }
 
-template <int LPI, int P, int DC, int RULE>
-static hipError_t launch_bp_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
-    const int wpb = cfg.waves_per_block;
-    const size_t lds = (size_t)wpb * (64 / LPI) * a.inst_bytes;
-    int64_t blocks;
-    if (a.persistent) blocks = cfg.blocks;
-    else blocks = (a.n_items + wpb - 1) / wpb;
-    hipLaunchKernelGGL((bp_kernel<LPI, P, DC, RULE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a);
-    return hipGetLastError();
+bool bp_layout(const BPArgs &a, int &mpad) {
+    int pv, pc;
+    passes_needed(a, pv, pc);
+    PassPair pp;
+    if (!pick_pair(pv, pc, pp)) return false;
+    mpad = 64 * pp.pc;
+    return true;
 }
 
-template <int P, int DC, int RULE>
+template <int PV, int PC, int DC, int RULE>
 static hipError_t launch_wave_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
     const int wpb = cfg.waves_per_block;
     const size_t lds = (size_t)wpb * a.inst_bytes;
     const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
-    hipLaunchKernelGGL((bp_wave_kernel<P, DC, RULE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a);
     return hipGetLastError();
 }
 
-template <int LPI, int P>
-static hipError_t launch_bp_p(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
-    if constexpr (LPI == 64) {
-        bool u6 = true;
-        for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
-        if (rule == 0) return u6 ? launch_wave_t<P, 6, 0>(a, cfg, s) : launch_wave_t<P, 8, 0>(a, cfg, s);
-        return u6 ? launch_wave_t<P, 6, 1>(a, cfg, s) : launch_wave_t<P, 8, 1>(a, cfg, s);
-    }
+template <int PV, int PC>
+static hipError_t launch_pair(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
     bool u6 = true;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
-    if (rule == 0) return u6 ? launch_bp_t<LPI, P, 6, 0>(a, cfg, s) : launch_bp_t<LPI, P, 8, 0>(a, cfg, s);
-    return u6 ? launch_bp_t<LPI, P, 6, 1>(a, cfg, s) : launch_bp_t<LPI, P, 8, 1>(a, cfg, s);
+    if (rule == 0) return u6 ? launch_wave_t<PV, PC, 6, 0>(a, cfg, s) : launch_wave_t<PV, PC, 8, 0>(a, cfg, s);
+    return u6 ? launch_wave_t<PV, PC, 6, 1>(a, cfg, s) : launch_wave_t<PV, PC, 8, 1>(a, cfg, s);
 }
 
 hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s) {
-    if (schedule != 0) return hipErrorInvalidValue;
-    const int P = pick_passes(cfg.lpi, passes_needed(a, cfg.lpi));
+    if (schedule != 0 || cfg.lpi != 64) return hipErrorInvalidValue;
+    int pv, pc;
+    passes_needed(a, pv, pc);
+    PassPair pp;
+    if (!pick_pair(pv, pc, pp)) return hipErrorInvalidValue;
 #ifndef MBBP_KERNEL_PROBE
-    switch (cfg.lpi * 100 + P) {
-    case 1603: return launch_bp_p<16, 3>(a, cfg, rule, s);
-    case 1606: return launch_bp_p<16, 6>(a, cfg, rule, s);
-    case 1609: return launch_bp_p<16, 9>(a, cfg, rule, s);
-    case 3203: return launch_bp_p<32, 3>(a, cfg, rule, s);
-    case 3205: return launch_bp_p<32, 5>(a, cfg, rule, s);
-    case 3209: return launch_bp_p<32, 9>(a, cfg, rule, s);
-    case 6402: return launch_bp_p<64, 2>(a, cfg, rule, s);
-    case 6403: return launch_bp_p<64, 3>(a, cfg, rule, s);
-    case 6405: return launch_bp_p<64, 5>(a, cfg, rule, s);
-    case 6409: return launch_bp_p<64, 9>(a, cfg, rule, s);
-    case 6414: return launch_bp_p<64, 14>(a, cfg, rule, s);
-    case 6416: return launch_bp_p<64, 16>(a, cfg, rule, s);
+    switch (pp.pv * 100 + pp.pc) {
+    case 101: return launch_pair<1, 1>(a, cfg, rule, s);
+    case 201: return launch_pair<2, 1>(a, cfg, rule, s);
+    case 202: return launch_pair<2, 2>(a, cfg, rule, s);
+    case 302: return launch_pair<3, 2>(a, cfg, rule, s);
+    case 303: return launch_pair<3, 3>(a, cfg, rule, s);
+    case 505: return launch_pair<5, 5>(a, cfg, rule, s);
+    case 909: return launch_pair<9, 9>(a, cfg, rule, s);
+    case 1414: return launch_pair<14, 14>(a, cfg, rule, s);
+    case 1616: return launch_pair<16, 16>(a, cfg, rule, s);
     }
 #else
-    (void)P; (void)rule; (void)s;
+    (void)rule; (void)s;
 #endif
     return hipErrorInvalidValue;
 }

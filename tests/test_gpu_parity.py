@@ -352,8 +352,8 @@ def test_launch_configs_bit_identical(pk, key, p):
     for part, h, (bp, rows), syn, tag in ((0, code.hz, bz, sx, "x"), (1, code.hx, bx, sz, "z")):
         r = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), wl.T, alpha=wl.alpha, precision="f32")
         ref[tag] = r
-    for lpi in (16, 32, 64):
-        for wpb, chunk in ((1, 1), (4, 7), (2, 64)):
+    for lpi in (64,):
+        for wpb, chunk in ((1, 1), (4, 7), (2, 64), (3, 1000)):
             for form in (0, 1):
                 try:
                     dec.set_config(form, lpi, wpb, chunk, 37 if form else 0)
