@@ -22,10 +22,6 @@
 
 #include "mbbp_device.h"
 
-#ifndef MBBP_BP_ATTR
-#define MBBP_BP_ATTR
-#endif
-
 namespace mbbp {
 
 // ----------------------------------------------------------------------------- helpers
@@ -294,7 +290,8 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
 // DC: 6 = every row has weight 6; 8 = rows of weight 2..8 with unused slots read
 // as +FLT_MAX (never a minimum, neutral for box-plus).
 template <int PV, int PC, int DC, int RULE>
-__global__ __launch_bounds__(256) MBBP_BP_ATTR void bp_wave_kernel(BPArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? 4 : 1)))
+void bp_wave_kernel(BPArgs a) {
     using LY = Layout<PC>;
     constexpr int Mpad = LY::Mpad;
     const int lane = threadIdx.x & 63;
