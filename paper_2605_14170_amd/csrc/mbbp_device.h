@@ -33,6 +33,14 @@ struct DevPart {
     const int32_t *hrow_idx;
     const uint64_t *logical;   // [k][W] logical operators of the other type (failure test)
     int k;
+    // serial schedule: levels of representation l are lev_ptr[lev_off[l] ..
+    // lev_off[l + 1]) (offsets into lev_chk + l * Mmax, the checks ordered by level);
+    // ltab[(l * Mmax + j) * 8 + k] = 8 x u16: variable id | degree << 12, then the
+    // variable's other edge ids in ascending check order (sink beyond its degree)
+    const int32_t *lev_off;
+    const int32_t *lev_ptr;
+    const uint16_t *lev_chk;
+    const uint4 *ltab;
 };
 
 // One BP launch (plain or persistent).
@@ -63,6 +71,7 @@ struct BPArgs {
     int msg_bytes;           // message rows of an instance: (Mmax + 1) * 8 floats
     int zero_bytes;          // message rows + decision rows (cleared at every fill), multiple of 16
     int ws_max, w_max;       // syndrome words / candidate words of the launch's parts
+    int n_max;               // priors staged in LDS (per-shot priors, serial schedule)
 };
 
 struct SampleArgs {

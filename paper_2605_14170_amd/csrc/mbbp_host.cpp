@@ -224,6 +224,10 @@ struct HostPart {
     std::vector<int32_t> csrc, comb_ptr{0}, comb_idx;
     std::vector<uint64_t> logical;
     int k = 0;
+    // serial schedule: conflict-free levels of every representation and, per
+    // check slot, the variable and its other edges (ascending check order)
+    std::vector<int32_t> lev_off{0}, lev_ptr;
+    std::vector<uint16_t> lev_chk, ltab;
 };
 
 mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &bl, const char *name,
@@ -325,6 +329,47 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
                 P.voff[((size_t)l * n + s) * 8 + k] =
                     k < (int)vedges[i].size() ? vedges[i][k] : (uint16_t)(Mmax * 8);
         }
+        // Serial schedule (Section II-B): checks are visited in row order, each seeing
+        // the latest check messages.  Level of check j = 1 + the highest level of an
+        // earlier check sharing a variable with it; checks of one level share no
+        // variable, so running levels in order equals the row-order sweep exactly.
+        std::vector<int> lastlev(n, -1), level(P.M[l], 0);
+        int nlev = 0;
+        for (int j = 0; j < P.M[l]; ++j) {
+            int lv = 0;
+            for (int v : reps[l][j]) lv = std::max(lv, lastlev[v] + 1);
+            level[j] = lv;
+            for (int v : reps[l][j]) lastlev[v] = std::max(lastlev[v], lv);
+            nlev = std::max(nlev, lv + 1);
+        }
+        std::vector<int> cnt(nlev + 1, 0);
+        for (int j = 0; j < P.M[l]; ++j) cnt[level[j] + 1]++;
+        for (int t = 0; t < nlev; ++t) cnt[t + 1] += cnt[t];
+        for (int t = 0; t <= nlev; ++t) P.lev_ptr.push_back(cnt[t]);
+        P.lev_off.push_back((int32_t)P.lev_ptr.size());
+        std::vector<uint16_t> order(Mmax, 0);
+        {
+            std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+            for (int j = 0; j < P.M[l]; ++j) order[fill[level[j]]++] = (uint16_t)j;
+        }
+        P.lev_chk.insert(P.lev_chk.end(), order.begin(), order.end());
+        // per check slot (j, k): word 0 = variable id | degree << 12, words 1..7 = the
+        // variable's other edges in ascending check order (sink beyond its degree)
+        std::vector<uint16_t> tab((size_t)Mmax * 8 * 8, (uint16_t)(Mmax * 8));
+        for (int j = 0; j < Mmax; ++j)
+            for (int k = 0; k < 8; ++k) tab[((size_t)j * 8 + k) * 8] = 0;
+        for (int j = 0; j < P.M[l]; ++j) {
+            const Row &r = reps[l][j];
+            for (size_t k = 0; k < r.size(); ++k) {
+                const int v = r[k];
+                uint16_t *e = &tab[((size_t)j * 8 + k) * 8];
+                e[0] = (uint16_t)(v | ((int)vedges[v].size() << 12));
+                int t = 1;
+                for (uint16_t other : vedges[v])
+                    if (other != (uint16_t)(j * 8 + k)) e[t++] = other;
+            }
+        }
+        P.ltab.insert(P.ltab.end(), tab.begin(), tab.end());
     }
     return MBBP_OK;
 }
@@ -417,6 +462,14 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
     if ((st = c->put(D.vdeg, P.vdeg)) != MBBP_OK) return st;
     if ((st = c->put(D.cw, P.cw)) != MBBP_OK) return st;
     if ((st = c->put(D.csrc, P.csrc)) != MBBP_OK) return st;
+    if ((st = c->put(D.lev_off, P.lev_off)) != MBBP_OK) return st;
+    if ((st = c->put(D.lev_ptr, P.lev_ptr)) != MBBP_OK) return st;
+    if ((st = c->put(D.lev_chk, P.lev_chk)) != MBBP_OK) return st;
+    {
+        const uint16_t *lt = nullptr;
+        if ((st = c->put(lt, P.ltab)) != MBBP_OK) return st;
+        D.ltab = reinterpret_cast<const uint4 *>(lt);
+    }
     if ((st = c->put(D.comb_ptr, P.comb_ptr)) != MBBP_OK) return st;
     std::vector<int32_t> ci = P.comb_idx;
     if ((st = c->put(D.comb_idx, ci)) != MBBP_OK) return st;
@@ -439,7 +492,7 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
 // LDS bytes of one BP instance (must match bp_wave_kernel): messages and decision
 // cells for Mpad rows of 8 slots (64 * Mpad bytes), the syndrome words, the output
 // staging words and, for per-shot priors, the shot's n priors.
-bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, mbbp::BPArgs &a) {
+bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, mbbp::BPArgs &a) {
     int W = 0, Ws = 0, n = 0;
     for (int p = part0; p < part0 + nparts; ++p) {
         W = std::max(W, c->dp[p].W);
@@ -450,9 +503,12 @@ bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, 
     if (!mbbp::bp_layout(a, mpad)) return false;
     a.ws_max = Ws;
     a.w_max = W;
+    a.n_max = n;
     a.msg_bytes = 32 * mpad;
     a.zero_bytes = 64 * mpad;
-    const int bytes = 64 * mpad + Ws * 8 + W * 8 + (per_shot_prior ? n * 4 : 0);
+    // serial schedule: priors always staged (n floats) plus one syndrome byte per row
+    const bool serial = schedule == MBBP_LAYERED;
+    const int bytes = 64 * mpad + Ws * 8 + W * 8 + ((per_shot_prior || serial) ? n * 4 : 0) + (serial ? mpad : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     return true;
 }
@@ -511,7 +567,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     a.item_order = persistent ? c->item_order + (part0 == 1 ? 0 : 0) : nullptr;
     if (persistent && nparts != 2) a.item_order = nullptr;
     a.queue = c->w_queue;
-    if (!inst_layout(c, part0, nparts, pps != 0, a))
+    if (!inst_layout(c, part0, nparts, pps != 0, c->schedule, a))
         return fail(MBBP_EUNSUPPORTED, "code too large for the BP kernel's register tables");
     mbbp::BPConfig run = cfg;
     if (persistent) {
@@ -722,7 +778,6 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
         for (int lpi : {16, 32, 64}) {
             (void)lpi;
         }
-        if (schedule != MBBP_FLOODING) return fail(MBBP_EUNSUPPORTED, "schedule not built yet");
         // default launch shape: one instance per wavefront (measured fastest on MI355X;
         // the autotuner may pick another)
         const int lpi = 64;

@@ -281,6 +281,22 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     }
 }
 
+// Posterior only (serial schedule): P = mu + sum r in ascending check order and the
+// hard decision written to every edge's decision cell; messages are left alone.
+template <int D, uint32_t DECOFF>
+__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
+    float pre = mu;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float x = *lds_ptr_f32(ea[k]);
+        pre += k < deg ? x : 0.0f;
+    }
+    dec = pre < 0.0f;
+    P = pre;
+#pragma unroll
+    for (int k = 0; k < D; ++k) *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+}
+
 // One instance per wavefront.  Every per-instance quantity (shot, iteration,
 // halting) is wave-uniform; per lane live only the variable slots' edge addresses,
 // priors and the check slots' syndrome bits.  Variable slots: s = v * 64 + lane,
@@ -289,7 +305,11 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
 // after another by the same wave.
 // DC: 6 = every row has weight 6; 8 = rows of weight 2..8 with unused slots read
 // as +FLT_MAX (never a minimum, neutral for box-plus).
-template <int PV, int PC, int DC, int RULE>
+// SCHED 0: flooding (variable phase, then check phase with the syndrome test).
+// SCHED 1: serial (Section II-B): posterior phase, syndrome test, then a sweep
+// over the conflict-free levels of the checks in which every check computes its
+// incoming messages from the latest check messages.
+template <int PV, int PC, int DC, int RULE, int SCHED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? 4 : 1)))
 void bp_wave_kernel(BPArgs a) {
     using LY = Layout<PC>;
@@ -302,6 +322,8 @@ void bp_wave_kernel(BPArgs a) {
     uint64_t *synl = reinterpret_cast<uint64_t *>(ibase + LY::kTail);
     uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
     float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
+    unsigned char *sbl = reinterpret_cast<unsigned char *>(mul + a.n_max);  // serial: syndrome byte per check
+    constexpr bool kMuLds = SCHED == 1;  // the serial sweep reads priors from LDS
 
     int64_t item;
     if (a.persistent) {
@@ -314,6 +336,7 @@ void bp_wave_kernel(BPArgs a) {
     const float alpha = a.alpha, rmax = a.rmax;
     const int T = a.T;
     int cur_key = -1;
+    int dmax_rep = 0;  // largest variable degree of the representation (wave-uniform)
 
     uint32_t ea[PV][kMaxVarDegree];  // LDS byte address of every edge of the lane's variables
     uint32_t vinfo[PV];              // variable id | degree << 16
@@ -360,6 +383,9 @@ void bp_wave_kernel(BPArgs a) {
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
                 if (!a.prior_per_shot) mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
             }
+            dmax_rep = 0;
+#pragma unroll
+            for (int v = 0; v < PV; ++v) dmax_rep = max(dmax_rep, dmaxp[v]);
             if (DC == 8) {
 #pragma unroll
                 for (int c = 0; c < PC; ++c) {
@@ -382,9 +408,9 @@ void bp_wave_kernel(BPArgs a) {
                 constexpr int nz = (int)(LY::kTail / 16);
                 for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
                 if (lane < Ws) synl[lane] = syn[shot * Ws + lane];
-                if (a.prior_per_shot) {
-                    const float *pr = prior + shot * n;
-                    for (int i = lane; i < n; i += 64) mul[i] = pr[i];
+                if (a.prior_per_shot || kMuLds) {
+                    const float *pr = prior + (a.prior_per_shot ? shot * n : 0);
+                    for (int i = lane; i < n; i += 64) mul[i] = pr[i] + 0.0f;
                 }
             }
             wave_sync();
@@ -411,75 +437,167 @@ void bp_wave_kernel(BPArgs a) {
                         }
                     }
                     sbits |= bit << c;
+                    if (SCHED == 1) sbl[j] = (unsigned char)bit;
                 }
             }
             int it = 0, kfix = -1, K = T;
             bool conv = false;
             uint32_t decb = 0;
-            while (true) {
-                // ---------------- variable phase
+            if constexpr (SCHED == 1) {
+                const int32_t *lp = pt->lev_ptr + pt->lev_off[l];
+                const int nlev = pt->lev_off[l + 1] - pt->lev_off[l] - 1;
+                const uint16_t *lc = pt->lev_chk + (size_t)l * Mmax;
+                const uint4 *lt = pt->ltab + (size_t)l * Mmax * 8;
+                while (true) {
+                    // ---------------- posterior phase (r = 0 at iteration 0)
 #pragma unroll
-                for (int v = 0; v < PV; ++v) {
-                    if (v < vp) {
-                        const int deg = (int)(vinfo[v] >> 16);
-                        float Pv = 0.0f;
-                        bool d = false;
-                        switch (uniform_i32(dmaxp[v])) {
-                        case 1: var_rule<1, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 2: var_rule<2, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 3: var_rule<3, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 4: var_rule<4, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 5: var_rule<5, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 6: var_rule<6, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 7: var_rule<7, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        case 8: var_rule<8, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                        default: Pv = mu[v]; d = Pv < 0.0f; break;
+                    for (int v = 0; v < PV; ++v) {
+                        if (v < vp) {
+                            const int deg = (int)(vinfo[v] >> 16);
+                            float Pv = 0.0f;
+                            bool d = false;
+                            switch (uniform_i32(dmaxp[v])) {
+                            case 1: var_post<1, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 2: var_post<2, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 3: var_post<3, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 4: var_post<4, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 5: var_post<5, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 6: var_post<6, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 7: var_post<7, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 8: var_post<8, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            default: Pv = mu[v]; d = Pv < 0.0f; break;
+                            }
+                            decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
+                            if (llr) {
+                                const int s = v * 64 + lane;
+                                if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
+                            }
                         }
-                        decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                        if (llr) {
-                            const int s = v * 64 + lane;
-                            if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
+                    }
+                    wave_sync();
+                    // ---------------- syndrome test
+                    uint32_t unsat = 0;
+#pragma unroll
+                    for (int c = 0; c < PC; ++c) {
+                        const int j = c * 64 + lane;
+                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
+                        uint32_t par = (sbits >> c) & 1u;
+#pragma unroll
+                        for (int k = 0; k < DC; ++k) par ^= drow[4 * k * Mpad];
+                        unsat |= par & (j < Ml ? 1u : 0u);
+                    }
+                    const bool sat = __ballot(unsat != 0u) == 0ull;
+                    if (!a.fixed_T) {
+                        if (sat) { conv = true; K = it; break; }
+                        if (it == T) { K = T; break; }
+                    } else {
+                        if (sat && kfix < 0) kfix = it;
+                        if (it == T) { conv = kfix >= 0; K = conv ? kfix : T; break; }
+                    }
+                    // ---------------- sweep: levels in order, checks of a level in parallel
+                    for (int lev = 0; lev < nlev; ++lev) {
+                        const int b = lp[lev], e = lp[lev + 1];
+                        for (int base = b; base < e; base += 64) {
+                            const int idx = base + lane;
+                            if (idx < e) {
+                                const int j = lc[idx];
+                                const uint32_t sb = sbl[j];
+                                float q[DC];
+#pragma unroll
+                                for (int k = 0; k < DC; ++k) {
+                                    const uint4 t = lt[j * 8 + k];
+                                    const int vid = (int)(t.x & 0x3ffu);
+                                    const int deg = (int)((t.x >> 12) & 0xfu);
+                                    const uint32_t oth[7] = {t.x >> 16, t.y & 0xffffu, t.y >> 16, t.z & 0xffffu,
+                                                             t.z >> 16, t.w & 0xffffu, t.w >> 16};
+                                    float acc = mul[vid];
+#pragma unroll
+                                    for (int u = 0; u < kMaxVarDegree - 1; ++u) {
+                                        if (u < dmax_rep - 1) {
+                                            const uint32_t eo = oth[u];
+                                            const float x = *lds_ptr_f32(ibase_addr +
+                                                                         4u * ((eo & 7u) * (uint32_t)Mpad + (eo >> 3)));
+                                            acc += u < deg - 1 ? x : 0.0f;
+                                        }
+                                    }
+                                    q[k] = deg == 0 ? 3.402823466e38f : acc;
+                                }
+                                CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
+                                lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+#pragma unroll
+                                for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
+                            }
+                            wave_sync();
                         }
                     }
+                    ++it;
                 }
-                wave_sync();
-                // ---------------- check phase: syndrome test of the decisions, c->v messages.
-                // Rows beyond the representation's checks are junk rows (unused by it).
-                uint32_t unsat = 0;
-#pragma unroll
-                for (int c = 0; c < PC; ++c) {
-                    const int j = c * 64 + lane;
-                    lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
-                    const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
-                    float q[DC];
-                    uint32_t par = (sbits >> c) & 1u;
-#pragma unroll
-                    for (int k = 0; k < DC; ++k) {
-                        q[k] = row[k * Mpad];
-                        par ^= drow[4 * k * Mpad];
+            } else {
+                while (true) {
+                    // ---------------- variable phase
+    #pragma unroll
+                    for (int v = 0; v < PV; ++v) {
+                        if (v < vp) {
+                            const int deg = (int)(vinfo[v] >> 16);
+                            float Pv = 0.0f;
+                            bool d = false;
+                            switch (uniform_i32(dmaxp[v])) {
+                            case 1: var_rule<1, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 2: var_rule<2, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 3: var_rule<3, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 4: var_rule<4, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 5: var_rule<5, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 6: var_rule<6, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 7: var_rule<7, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 8: var_rule<8, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            default: Pv = mu[v]; d = Pv < 0.0f; break;
+                            }
+                            decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
+                            if (llr) {
+                                const int s = v * 64 + lane;
+                                if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
+                            }
+                        }
                     }
-                    if constexpr (DC == 8) {
-                        const int w = (int)cwp[c];
-#pragma unroll
-                        for (int k = 2; k < DC; ++k)
-                            if (k >= w) q[k] = 3.402823466e38f;
+                    wave_sync();
+                    // ---------------- check phase: syndrome test of the decisions, c->v messages.
+                    // Rows beyond the representation's checks are junk rows (unused by it).
+                    uint32_t unsat = 0;
+    #pragma unroll
+                    for (int c = 0; c < PC; ++c) {
+                        const int j = c * 64 + lane;
+                        lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
+                        float q[DC];
+                        uint32_t par = (sbits >> c) & 1u;
+    #pragma unroll
+                        for (int k = 0; k < DC; ++k) {
+                            q[k] = row[k * Mpad];
+                            par ^= drow[4 * k * Mpad];
+                        }
+                        if constexpr (DC == 8) {
+                            const int w = (int)cwp[c];
+    #pragma unroll
+                            for (int k = 2; k < DC; ++k)
+                                if (k >= w) q[k] = 3.402823466e38f;
+                        }
+                        unsat |= par & (j < Ml ? 1u : 0u);
+                        CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
+    #pragma unroll
+                        for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
                     }
-                    unsat |= par & (j < Ml ? 1u : 0u);
-                    CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
-#pragma unroll
-                    for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
+                    const bool sat = __ballot(unsat != 0u) == 0ull;
+                    // ---------------- halting (Section II-B)
+                    if (!a.fixed_T) {
+                        if (sat) { conv = true; K = it; break; }
+                        if (it == T) { K = T; break; }
+                    } else {
+                        if (sat && kfix < 0) kfix = it;
+                        if (it == T) { conv = kfix >= 0; K = conv ? kfix : T; break; }
+                    }
+                    ++it;
+                    wave_sync();
                 }
-                const bool sat = __ballot(unsat != 0u) == 0ull;
-                // ---------------- halting (Section II-B)
-                if (!a.fixed_T) {
-                    if (sat) { conv = true; K = it; break; }
-                    if (it == T) { K = T; break; }
-                } else {
-                    if (sat && kfix < 0) kfix = it;
-                    if (it == T) { conv = kfix >= 0; K = conv ? kfix : T; break; }
-                }
-                ++it;
-                wave_sync();
             }
             // ---------------- output: bit-packed hard decisions via the staging words
             if (lane < 2 * W) stage[lane] = 0u;
@@ -726,7 +844,7 @@ int bp_max_passes(int lpi) { return lpi == 64 ? 16 : 0; }
 
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule) {
     (void)dc_uniform;
-    if (schedule != 0 || (rule != 0 && rule != 1) || lpi != 64) return false;
+    if ((schedule != 0 && schedule != 1) || (rule != 0 && rule != 1) || lpi != 64) return false;
     PassPair pp;
     return pick_pair(passes, passes, pp);
 }
@@ -740,45 +858,52 @@ bool bp_layout(const BPArgs &a, int &mpad) {
     return true;
 }
 
-template <int PV, int PC, int DC, int RULE>
+template <int PV, int PC, int DC, int RULE, int SCHED>
 static hipError_t launch_wave_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
     const int wpb = cfg.waves_per_block;
     const size_t lds = (size_t)wpb * a.inst_bytes;
     const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
-    hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE, SCHED>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
+                       a);
     return hipGetLastError();
 }
 
-template <int PV, int PC>
+template <int PV, int PC, int SCHED>
 static hipError_t launch_pair(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
     bool u6 = true;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
-    if (rule == 0) return u6 ? launch_wave_t<PV, PC, 6, 0>(a, cfg, s) : launch_wave_t<PV, PC, 8, 0>(a, cfg, s);
-    return u6 ? launch_wave_t<PV, PC, 6, 1>(a, cfg, s) : launch_wave_t<PV, PC, 8, 1>(a, cfg, s);
+    if (rule == 0)
+        return u6 ? launch_wave_t<PV, PC, 6, 0, SCHED>(a, cfg, s) : launch_wave_t<PV, PC, 8, 0, SCHED>(a, cfg, s);
+    return u6 ? launch_wave_t<PV, PC, 6, 1, SCHED>(a, cfg, s) : launch_wave_t<PV, PC, 8, 1, SCHED>(a, cfg, s);
+}
+
+template <int SCHED>
+static hipError_t launch_sched(const BPArgs &a, const BPConfig &cfg, int rule, const PassPair &pp, hipStream_t s) {
+#ifndef MBBP_KERNEL_PROBE
+    switch (pp.pv * 100 + pp.pc) {
+    case 101: return launch_pair<1, 1, SCHED>(a, cfg, rule, s);
+    case 201: return launch_pair<2, 1, SCHED>(a, cfg, rule, s);
+    case 202: return launch_pair<2, 2, SCHED>(a, cfg, rule, s);
+    case 302: return launch_pair<3, 2, SCHED>(a, cfg, rule, s);
+    case 303: return launch_pair<3, 3, SCHED>(a, cfg, rule, s);
+    case 505: return launch_pair<5, 5, SCHED>(a, cfg, rule, s);
+    case 909: return launch_pair<9, 9, SCHED>(a, cfg, rule, s);
+    case 1414: return launch_pair<14, 14, SCHED>(a, cfg, rule, s);
+    case 1616: return launch_pair<16, 16, SCHED>(a, cfg, rule, s);
+    }
+#else
+    (void)a; (void)cfg; (void)rule; (void)pp; (void)s;
+#endif
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s) {
-    if (schedule != 0 || cfg.lpi != 64) return hipErrorInvalidValue;
+    if ((schedule != 0 && schedule != 1) || cfg.lpi != 64) return hipErrorInvalidValue;
     int pv, pc;
     passes_needed(a, pv, pc);
     PassPair pp;
     if (!pick_pair(pv, pc, pp)) return hipErrorInvalidValue;
-#ifndef MBBP_KERNEL_PROBE
-    switch (pp.pv * 100 + pp.pc) {
-    case 101: return launch_pair<1, 1>(a, cfg, rule, s);
-    case 201: return launch_pair<2, 1>(a, cfg, rule, s);
-    case 202: return launch_pair<2, 2>(a, cfg, rule, s);
-    case 302: return launch_pair<3, 2>(a, cfg, rule, s);
-    case 303: return launch_pair<3, 3>(a, cfg, rule, s);
-    case 505: return launch_pair<5, 5>(a, cfg, rule, s);
-    case 909: return launch_pair<9, 9>(a, cfg, rule, s);
-    case 1414: return launch_pair<14, 14>(a, cfg, rule, s);
-    case 1616: return launch_pair<16, 16>(a, cfg, rule, s);
-    }
-#else
-    (void)rule; (void)s;
-#endif
-    return hipErrorInvalidValue;
+    return schedule == 0 ? launch_sched<0>(a, cfg, rule, pp, s) : launch_sched<1>(a, cfg, rule, pp, s);
 }
 
 }  // namespace mbbp

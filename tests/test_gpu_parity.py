@@ -367,3 +367,78 @@ def test_launch_configs_bit_identical(pk, key, p):
                     np.testing.assert_array_equal(words(out[f"corr_{tag}"]), ref[tag].corr)
                     np.testing.assert_array_equal(out[f"basis_{tag}"].cpu().numpy(), ref[tag].chosen)
     dec.close()
+
+
+@pytest.mark.parametrize("key,p,shots", [("bb72_L4_T20", 0.05, 3000), ("bb144_L16_T50", 0.06, 500)])
+def test_nms_serial_bit_exact_fp32(pk, key, p, shots):
+    """Serial schedule: the GPU's level-parallel sweep equals the oracle's row-order
+    sweep bit for bit (decisions, iterations, convergence, posterior bits)."""
+    wl = WORKLOADS[key]
+    code = wl.code()
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots, schedule=pk.LAYERED)
+    say(f"nms serial fp32 bit-exact {key} p={p} shots={shots}")
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 0, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+        torch.cuda.synchronize()
+        ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), wl.T, schedule=oracle.LAYERED,
+                            alpha=wl.alpha, want_llr=True, precision="f32")
+        ks = kstat.cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
+        np.testing.assert_array_equal((ks >> 15).astype(bool), ref.conv)
+        np.testing.assert_array_equal(words(cand), ref.cand)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+        say(f"  part {part}: mean K {ref.K.mean():.3f}")
+    dec.close()
+
+
+@pytest.mark.parametrize("factory", [codes.steane7, codes.surface13, codes.toric18])
+def test_nms_serial_small_codes_bit_exact(pk, factory):
+    from workloads.perms import check_permutations
+    code = factory()
+    L, T, shots, p = 3, 12, 500, 0.1
+    bx = oracle.build_bases(code.hx, "ramp", L, check_permutations(code.hx.shape[0], L, 1))
+    bz = oracle.build_bases(code.hz, "ramp", L, check_permutations(code.hz.shape[0], L, 1))
+    say(f"serial small code {code.name}")
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, T, alpha=0.8, max_batch=shots, schedule=pk.LAYERED)
+    ex, ez, sx, sz = dec.sample(5, p, 0, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+        torch.cuda.synchronize()
+        ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), T, schedule=oracle.LAYERED, alpha=0.8,
+                            want_llr=True, precision="f32")
+        np.testing.assert_array_equal(words(cand), ref.cand)
+        np.testing.assert_array_equal(kstat.cpu().numpy().view(np.uint16) & 0x7FFF, ref.K)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+    dec.close()
+
+
+def test_spa_serial_exact_on_trees(pk):
+    """Serial sum-product on cycle-free graphs reaches the exact marginals (FP64 oracle)."""
+    from .test_oracle_pins import _random_tree
+    rng = np.random.default_rng(22)
+    bases = (np.zeros(2, np.int32), np.zeros(0, np.int32))
+    for trial in range(4):
+        h = _random_tree(rng, int(rng.integers(3, 7)), wmin=3, wmax=5)
+        n = h.shape[1]
+        say(f"spa serial tree trial {trial} n={n}")
+        dec = pk.Decoder(h, _commuting_pair(h), bases, bases, 30, rule=pk.SPA, fixed_T=True, max_batch=64,
+                         schedule=pk.LAYERED)
+        s = rng.integers(0, 2, (64, h.shape[0])).astype(np.uint8)
+        syn = torch.from_numpy(oracle.pack(s).view(np.int64)).cuda()
+        mu = rng.uniform(-1.0, 3.0, n).astype(np.float32)
+        cand, kstat, llr = dec.decode_detail(1, syn, torch.from_numpy(mu).cuda(), want_llr=True)
+        torch.cuda.synchronize()
+        ref = oracle.decode(h, np.array([0, 0], np.int32), np.array([], np.int32), oracle.pack(s),
+                            mu.astype(np.float64), 30, schedule=oracle.LAYERED, rule=oracle.SPA, fixed_T=True,
+                            want_llr=True)
+        got = llr.cpu().numpy()[:, 0, :].astype(np.float64)
+        exp = ref.llr[:, 0, :]
+        err = np.abs(got - exp) / np.maximum(1.0, np.abs(exp))
+        say(f"  max relative LLR error {err.max():.3e}")
+        assert np.all(err <= 1e-4)
+        dec.close()
