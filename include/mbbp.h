@@ -177,7 +177,8 @@ enum {
 
 /* The whole path for shots [shot0, shot0 + shots): noise (mbbp_sample), the
  * batched decoder, the decision and the failure test, replayed from a HIP graph
- * captured on first use for this `shots`.  counters: device int64
+ * captured on first use for this `shots` (direct launches while BP timing is
+ * enabled, see mbbp_set_timing, or with mbbp_set_graph(ctx, 0)).  counters: device int64
  * [MBBP_NUM_COUNTERS], ACCUMULATED into (the caller zeroes it).  Uniform
  * priors log((1 - 2p/3) / (2p/3)) for both parts. */
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
@@ -196,6 +197,17 @@ typedef struct {
 } mbbp_launch_config;
 mbbp_status mbbp_set_config(mbbp_ctx *ctx, int32_t form, const mbbp_launch_config *cfg);
 mbbp_status mbbp_get_config(mbbp_ctx *ctx, int32_t form, mbbp_launch_config *cfg);
+
+/* Autotuner: times the candidate launch configurations of `form` (0 plain,
+ * 1 batched) on `shots` synthetic shots drawn with (seed, p) and keeps the
+ * fastest; *chosen (may be NULL) receives it.  Synchronous.  Outputs of every
+ * later call are unchanged bit for bit (only the launch shape differs). */
+mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, int64_t shots,
+                          mbbp_launch_config *chosen);
+
+/* mbbp_run replays a HIP graph captured per `shots` (enable = 1, default) or
+ * launches its kernels directly (enable = 0); results are identical. */
+mbbp_status mbbp_set_graph(mbbp_ctx *ctx, int32_t enable);
 
 /* Event timing of the BP kernel.  While enabled, every BP kernel launch of this
  * context is bracketed by HIP events recorded on the launch's stream.

@@ -252,6 +252,17 @@ class Decoder:
         return dict(lanes_per_instance=cfg.lanes_per_instance, waves_per_block=cfg.waves_per_block,
                     chunk=cfg.chunk, blocks=cfg.blocks)
 
+    def autotune(self, form: int, seed: int = 12345, p: float = 0.05, shots: int = 65536) -> dict:
+        """Time the candidate launch shapes of `form` and keep the fastest."""
+        cfg = _lib.LaunchConfig()
+        _lib.check(_lib.lib().mbbp_autotune(self._ctx, int(form), int(seed), float(p), int(shots),
+                                            ctypes.byref(cfg)), "mbbp_autotune")
+        return dict(lanes_per_instance=cfg.lanes_per_instance, waves_per_block=cfg.waves_per_block,
+                    chunk=cfg.chunk, blocks=cfg.blocks)
+
+    def set_graph(self, enable: bool) -> None:
+        _lib.check(_lib.lib().mbbp_set_graph(self._ctx, 1 if enable else 0), "mbbp_set_graph")
+
     def set_timing(self, enable: bool) -> None:
         _lib.check(_lib.lib().mbbp_set_timing(self._ctx, 1 if enable else 0), "mbbp_set_timing")
 

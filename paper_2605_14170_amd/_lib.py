@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
             "mbbp_set_timing": ([P, i32], i32),
             "mbbp_set_config": ([P, i32, ctypes.POINTER(LaunchConfig)], i32),
             "mbbp_get_config": ([P, i32, ctypes.POINTER(LaunchConfig)], i32),
+            "mbbp_autotune": ([P, i32, u64, dbl, i64, ctypes.POINTER(LaunchConfig)], i32),
+            "mbbp_set_graph": ([P, i32], i32),
             "mbbp_bp_time": ([P, P, P, i32], i32),
         }
         for name, (args, res) in sig.items():
@@ -98,4 +100,4 @@ def check(status: int, where: str) -> None:
 EXPORTED = ["mbbp_params_default", "mbbp_create", "mbbp_destroy", "mbbp_decode", "mbbp_decode_batched",
             "mbbp_decode_detail", "mbbp_sample", "mbbp_failures", "mbbp_run", "mbbp_subtrees",
             "mbbp_build_bases", "mbbp_logicals", "mbbp_edge_counts", "mbbp_last_error", "mbbp_set_timing",
-            "mbbp_bp_time", "mbbp_set_config", "mbbp_get_config"]
+            "mbbp_bp_time", "mbbp_set_config", "mbbp_get_config", "mbbp_autotune", "mbbp_set_graph"]

@@ -74,6 +74,27 @@ struct BPArgs {
     int n_max;               // priors staged in LDS (per-shot priors, serial schedule)
 };
 
+// Per-call parameters of the captured whole-path graph, written on device by the
+// graph's first node (the only node whose parameters change between replays).
+struct RunDesc {
+    uint64_t seed;
+    int64_t shot0;
+    uint64_t t1, t2, t3;
+    int64_t *counters;       // caller's counters, accumulated at the end of the graph
+};
+
+struct RunPrepArgs {
+    RunDesc d;
+    RunDesc *desc;           // where the descriptor is stored
+    float *prior0, *prior1;
+    int n;
+    float mu;
+    int *kmax;
+    int64_t shots;
+    unsigned long long *queue;
+    int64_t *counters;       // internal counters cleared here
+};
+
 struct SampleArgs {
     DevPart part[2];         // part[0] uses H_Z (syn_x), part[1] uses H_X (syn_z)
     int n;
@@ -82,7 +103,7 @@ struct SampleArgs {
     int64_t shot0, shots;
     uint64_t *err[2];        // [shots][W]  e_X, e_Z
     uint64_t *syn[2];        // [shots][Ws] s_X = H_Z e_X, s_Z = H_X e_Z
-    const int64_t *desc;     // optional device (seed, shot0) override for graph replay, or null
+    const RunDesc *desc;     // graph replay: seed, shot0 and thresholds read from here (or null)
 };
 
 struct SelectArgs {
@@ -122,10 +143,12 @@ hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_fail(const FailArgs &a, hipStream_t s);
 hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncounters, hipStream_t s);
-// Per-run preparation: uniform priors mu for both parts, per-shot max-iteration
-// scratch cleared, work-queue counter cleared.
-hipError_t launch_run_prep(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
-                           unsigned long long *queue, hipStream_t s);
+// Per-run preparation: descriptor stored, uniform priors mu for both parts, per-shot
+// max-iteration scratch, work-queue counter and internal counters cleared.
+hipError_t launch_run_prep(const RunPrepArgs &a, hipStream_t s);
+// Adds the internal counters into the caller's (desc->counters).
+hipError_t launch_accumulate(const int64_t *src, const RunDesc *desc, int nc, hipStream_t s);
+const void *run_prep_kernel_ptr();
 int bp_max_passes(int lpi);  // register slots available per lane for this lpi
 // Rows per instance (Mpad = 64 * check passes) of the kernel a launch would use; false if none fits.
 bool bp_layout(const BPArgs &a, int &mpad);

@@ -390,6 +390,7 @@ struct RunGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t prep = nullptr;
+    hipKernelNodeParams prep_params{};
 };
 
 struct mbbp_ctx {
@@ -410,7 +411,7 @@ struct mbbp_ctx {
     float *w_prior[2]{};
     int *w_kmax = nullptr;
     int64_t *w_counters = nullptr;
-    int64_t *w_desc = nullptr;
+    mbbp::RunDesc *w_desc = nullptr;
     unsigned long long *w_queue = nullptr;
     int32_t *item_order = nullptr;
     int cu_count = 256;
@@ -418,6 +419,7 @@ struct mbbp_ctx {
     mbbp::BPConfig batched_cfg{16, 4, 8, 0};
     hipStream_t capture_stream = nullptr;
     std::map<int64_t, RunGraph> graphs;
+    bool use_graph = true;  // mbbp_run replays a captured graph
     // BP kernel event timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -526,6 +528,8 @@ mbbp_status ensure_run_workspace(mbbp_ctx *c) {
         if ((st = c->alloc(c->w_basis[p], (size_t)B)) != MBBP_OK) return st;
         if ((st = c->alloc(c->w_prior[p], (size_t)c->n)) != MBBP_OK) return st;
     }
+    if ((st = c->alloc(c->w_counters, (size_t)MBBP_NUM_COUNTERS)) != MBBP_OK) return st;
+    if ((st = c->alloc(c->w_desc, 1)) != MBBP_OK) return st;
     return c->alloc(c->w_kmax, (size_t)B);
 }
 
@@ -934,29 +938,30 @@ mbbp_status mbbp_failures(mbbp_ctx *ctx, int64_t shots, const uint64_t *err_x, c
     return MBBP_OK;
 }
 
-mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, int64_t *counters,
-                     void *hip_stream) {
-    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
-    if (!(p > 0.0 && p < 1.5)) return fail(MBBP_EINVAL, "p must be in (0, 1.5) for the uniform prior");
-    if (shots < 1 || shots > ctx->params.max_batch || shot0 < 0) return fail(MBBP_EINVAL, "shots out of range");
-    if (!counters) return fail(MBBP_EINVAL, "null counters");
-    mbbp_status st = ensure_run_workspace(ctx);
-    if (st != MBBP_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const double q = 2.0 * p / 3.0;
-    const float mu = (float)std::log((1.0 - q) / q);
-    hipError_t e = mbbp::launch_run_prep(ctx->w_prior[0], ctx->w_prior[1], ctx->n, mu, ctx->w_kmax, shots,
-                                         ctx->w_queue, s);
+// The whole path of one call, enqueued on s: descriptor and clearing (prep), noise
+// and syndromes, persistent BP, decision with counters, failure test, counters
+// added into the caller's.  Every node reads its per-call values from the device
+// descriptor, so a captured copy is replayed by changing only the prep node.
+static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int64_t shots, hipStream_t s) {
+    hipError_t e = mbbp::launch_run_prep(prep, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("prep launch: ") + hipGetErrorString(e));
-    if ((st = mbbp_sample(ctx, seed, p, shot0, shots, ctx->w_err[0], ctx->w_err[1], ctx->w_syn[0], ctx->w_syn[1],
-                          hip_stream)) != MBBP_OK)
-        return st;
+    mbbp::SampleArgs sa{};
+    sa.part[0] = ctx->dp[0];
+    sa.part[1] = ctx->dp[1];
+    sa.n = ctx->n;
+    sa.shots = shots;
+    sa.err[0] = ctx->w_err[0]; sa.err[1] = ctx->w_err[1];
+    sa.syn[0] = ctx->w_syn[0]; sa.syn[1] = ctx->w_syn[1];
+    sa.desc = ctx->w_desc;
+    e = mbbp::launch_sample(sa, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("sample launch: ") + hipGetErrorString(e));
     const uint64_t *sy[2] = {ctx->w_syn[0], ctx->w_syn[1]};
     const float *pr[2] = {ctx->w_prior[0], ctx->w_prior[1]};
     float *ll[2] = {nullptr, nullptr};
+    mbbp_status st;
     if ((st = run_bp(ctx, 0, 2, shots, sy, pr, 0, ctx->cand, ctx->kstat, ll, true, s)) != MBBP_OK) return st;
-    if ((st = run_select(ctx, 0, 2, shots, ctx->w_corr, ctx->w_conv, ctx->w_basis, counters, ctx->w_kmax, s)) !=
-        MBBP_OK)
+    if ((st = run_select(ctx, 0, 2, shots, ctx->w_corr, ctx->w_conv, ctx->w_basis, ctx->w_counters, ctx->w_kmax,
+                         s)) != MBBP_OK)
         return st;
     mbbp::FailArgs a{};
     a.part[0] = ctx->dp[0];
@@ -965,10 +970,92 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     a.err[0] = ctx->w_err[0]; a.err[1] = ctx->w_err[1];
     a.corr[0] = ctx->w_corr[0]; a.corr[1] = ctx->w_corr[1];
     a.fail = nullptr;
-    a.counters = counters;
+    a.counters = ctx->w_counters;
     a.kmax_shot = ctx->w_kmax;
     e = mbbp::launch_fail(a, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("failure launch: ") + hipGetErrorString(e));
+    e = mbbp::launch_accumulate(ctx->w_counters, ctx->w_desc, MBBP_NUM_COUNTERS, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("accumulate launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int64_t shots, RunGraph &g) {
+    if (!ctx->capture_stream) MBBP_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    MBBP_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    mbbp_status st = run_enqueue(ctx, prep, shots, ctx->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (st != MBBP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    g.graph = graph;
+    size_t count = 0;
+    MBBP_HIP(hipGraphGetNodes(graph, nullptr, &count));
+    std::vector<hipGraphNode_t> nodes(count);
+    MBBP_HIP(hipGraphGetNodes(graph, nodes.data(), &count));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        MBBP_HIP(hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        MBBP_HIP(hipGraphKernelNodeGetParams(nd, &kp));
+        if (kp.func == mbbp::run_prep_kernel_ptr()) {
+            g.prep = nd;
+            g.prep_params = kp;
+        }
+    }
+    if (!g.prep) return fail(MBBP_EDEVICE, "captured graph has no preparation node");
+    MBBP_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, int64_t *counters,
+                     void *hip_stream) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (!(p > 0.0 && p < 1.5) || p > 1.0) return fail(MBBP_EINVAL, "p must be in (0, 1]");
+    if (shots < 1 || shots > ctx->params.max_batch || shot0 < 0) return fail(MBBP_EINVAL, "shots out of range");
+    if (!counters) return fail(MBBP_EINVAL, "null counters");
+    mbbp_status st = ensure_run_workspace(ctx);
+    if (st != MBBP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const double q = 2.0 * p / 3.0;
+    mbbp::RunPrepArgs prep{};
+    prep.d.seed = seed;
+    prep.d.shot0 = shot0;
+    uint64_t t[3];
+    thresholds(p, t);
+    prep.d.t1 = t[0]; prep.d.t2 = t[1]; prep.d.t3 = t[2];
+    prep.d.counters = counters;
+    prep.desc = ctx->w_desc;
+    prep.prior0 = ctx->w_prior[0];
+    prep.prior1 = ctx->w_prior[1];
+    prep.n = ctx->n;
+    prep.mu = (float)std::log((1.0 - q) / q);
+    prep.kmax = ctx->w_kmax;
+    prep.shots = shots;
+    prep.queue = ctx->w_queue;
+    prep.counters = ctx->w_counters;
+    if (ctx->timing || !ctx->use_graph) return run_enqueue(ctx, prep, shots, s);  // events need direct launches
+    auto it = ctx->graphs.find(shots);
+    if (it == ctx->graphs.end()) {
+        RunGraph g;
+        st = capture_run_graph(ctx, prep, shots, g);
+        if (st != MBBP_OK) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            return st;
+        }
+        it = ctx->graphs.emplace(shots, g).first;
+    }
+    RunGraph &g = it->second;
+    hipKernelNodeParams kp = g.prep_params;
+    void *args[] = {&prep};
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    MBBP_HIP(hipGraphExecKernelNodeSetParams(g.exec, g.prep, &kp));
+    MBBP_HIP(hipGraphLaunch(g.exec, s));
     return MBBP_OK;
 }
 
@@ -1003,6 +1090,82 @@ mbbp_status mbbp_get_config(mbbp_ctx *ctx, int32_t form, mbbp_launch_config *cfg
     cfg->waves_per_block = b.waves_per_block;
     cfg->chunk = b.chunk;
     cfg->blocks = b.blocks;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_set_graph(mbbp_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    ctx->use_graph = enable != 0;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, int64_t shots,
+                          mbbp_launch_config *chosen) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (form != 0 && form != 1) return fail(MBBP_EINVAL, "form must be 0 (plain) or 1 (batched)");
+    if (!(p > 0.0 && p <= 1.0)) return fail(MBBP_EINVAL, "p must be in (0, 1]");
+    if (shots < 1 || shots > ctx->params.max_batch) return fail(MBBP_EINVAL, "shots out of range");
+    mbbp_status st = ensure_run_workspace(ctx);
+    if (st != MBBP_OK) return st;
+    if (!ctx->capture_stream) MBBP_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipStream_t s = ctx->capture_stream;
+    if ((st = mbbp_sample(ctx, seed, p, 0, shots, ctx->w_err[0], ctx->w_err[1], ctx->w_syn[0], ctx->w_syn[1], s)) !=
+        MBBP_OK)
+        return st;
+    const double q = 2.0 * p / 3.0;
+    std::vector<float> mu(ctx->n, (float)std::log((1.0 - q) / q));
+    for (int pt = 0; pt < 2; ++pt)
+        MBBP_HIP(hipMemcpyAsync(ctx->w_prior[pt], mu.data(), mu.size() * 4, hipMemcpyHostToDevice, s));
+    std::vector<mbbp::BPConfig> cands;
+    const int cu = ctx->cu_count;
+    if (form == 1) {
+        for (int wpb : {2, 4})
+            for (int chunk : {4, 16, 64})
+                for (int bpc : {2, 4, 8}) cands.push_back({64, wpb, chunk, cu * bpc});
+    } else {
+        for (int wpb : {1, 2, 4})
+            for (int chunk : {1, 4, 16, 64}) cands.push_back({64, wpb, chunk, 0});
+    }
+    mbbp::BPConfig &slot = form == 0 ? ctx->plain_cfg : ctx->batched_cfg;
+    const mbbp::BPConfig keep = slot;
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    hipEvent_t e0, e1;
+    MBBP_HIP(hipEventCreate(&e0));
+    MBBP_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    mbbp::BPConfig best = keep;
+    for (const mbbp::BPConfig &cfg : cands) {
+        slot = cfg;
+        float total = 0.0f;
+        for (int rep = 0; rep < 3 && st == MBBP_OK; ++rep) {
+            if (rep == 1) (void)hipEventRecord(e0, s);
+            st = decode_common(ctx, shots, ctx->w_syn[0], ctx->w_syn[1], ctx->w_prior[0], ctx->w_prior[1], 0,
+                               ctx->w_corr[0], ctx->w_corr[1], ctx->w_conv[0], ctx->w_conv[1], ctx->w_basis[0],
+                               ctx->w_basis[1], s, form == 1);
+        }
+        if (st != MBBP_OK) break;
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&total, e0, e1) != hipSuccess) {
+            st = fail(MBBP_EDEVICE, "autotune timing failed");
+            break;
+        }
+        if (total < best_ms) {
+            best_ms = total;
+            best = cfg;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->timing = timing;
+    slot = st == MBBP_OK ? best : keep;
+    if (st != MBBP_OK) return st;
+    if (chosen) {
+        chosen->lanes_per_instance = best.lpi;
+        chosen->waves_per_block = best.waves_per_block;
+        chosen->chunk = best.chunk;
+        chosen->blocks = best.blocks;
+    }
     return MBBP_OK;
 }
 

@@ -24,6 +24,8 @@
 
 namespace mbbp {
 
+constexpr int MBBP_NUM_COUNTERS_DEV = 8;
+
 // ----------------------------------------------------------------------------- helpers
 
 __device__ __forceinline__ void wave_sync() {
@@ -91,7 +93,14 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(SampleArgs a) {
     const int t = threadIdx.x;
     uint64_t seed = a.seed;
     int64_t shot0 = a.shot0;
-    if (a.desc) { seed = (uint64_t)a.desc[0]; shot0 = a.desc[1]; }
+    uint64_t t1 = a.t1, t2 = a.t2, t3 = a.t3;
+    if (a.desc) {
+        seed = a.desc->seed;
+        shot0 = a.desc->shot0;
+        t1 = a.desc->t1;
+        t2 = a.desc->t2;
+        t3 = a.desc->t3;
+    }
     const int64_t s = (int64_t)blockIdx.x * kSampleBlock + t;
     const bool live = s < a.shots;
     const int n = a.n;
@@ -108,8 +117,8 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(SampleArgs a) {
                 const uint64_t u = (o[sub >> 1] >> (32 * (sub & 1))) & 0xffffffffull;
                 const int bit = b8 * 8 + sub;
                 if (q0 + sub < n) {
-                    const uint64_t xb = (u < a.t2) ? 1ull : 0ull;              // X or Y
-                    const uint64_t zb = (u >= a.t1 && u < a.t3) ? 1ull : 0ull;  // Y or Z
+                    const uint64_t xb = (u < t2) ? 1ull : 0ull;            // X or Y
+                    const uint64_t zb = (u >= t1 && u < t3) ? 1ull : 0ull;  // Y or Z
                     bx |= xb << bit;
                     bz |= zb << bit;
                 }
@@ -775,24 +784,38 @@ __global__ void reset_kernel(unsigned long long *queue, int64_t *counters, int n
     if (counters && t < nc) counters[t] = 0;
 }
 
-__global__ void run_prep_kernel(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
-                                unsigned long long *queue) {
+__global__ void run_prep_kernel(RunPrepArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        prior0[i] = mu;
-        prior1[i] = mu;
+    if (i < a.n) {
+        a.prior0[i] = a.mu;
+        a.prior1[i] = a.mu;
     }
-    if (i < shots) kmax[i] = 0;
-    if (i == 0 && queue) *queue = 0ull;
+    if (i < a.shots) a.kmax[i] = 0;
+    if (i == 0) {
+        *a.desc = a.d;
+        if (a.queue) *a.queue = 0ull;
+    }
+    if (a.counters && i < MBBP_NUM_COUNTERS_DEV) a.counters[i] = 0;
 }
+
+__global__ void accumulate_kernel(const int64_t *src, const RunDesc *desc, int nc) {
+    const int t = threadIdx.x;
+    if (t < nc && desc->counters) atomicAdd((unsigned long long *)&desc->counters[t], (unsigned long long)src[t]);
+}
+
+const void *run_prep_kernel_ptr() { return reinterpret_cast<const void *>(&run_prep_kernel); }
 
 // ----------------------------------------------------------------------------- launchers
 
-hipError_t launch_run_prep(float *prior0, float *prior1, int n, float mu, int *kmax, int64_t shots,
-                           unsigned long long *queue, hipStream_t s) {
-    const int64_t total = shots > n ? shots : n;
-    hipLaunchKernelGGL(run_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, prior0, prior1,
-                       n, mu, kmax, shots, queue);
+hipError_t launch_run_prep(const RunPrepArgs &a, hipStream_t s) {
+    int64_t total = a.shots > a.n ? a.shots : a.n;
+    if (total < MBBP_NUM_COUNTERS_DEV) total = MBBP_NUM_COUNTERS_DEV;
+    hipLaunchKernelGGL(run_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const int64_t *src, const RunDesc *desc, int nc, hipStream_t s) {
+    hipLaunchKernelGGL(accumulate_kernel, dim3(1), dim3(64), 0, s, src, desc, nc);
     return hipGetLastError();
 }
 

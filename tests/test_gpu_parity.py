@@ -442,3 +442,54 @@ def test_spa_serial_exact_on_trees(pk):
         say(f"  max relative LLR error {err.max():.3e}")
         assert np.all(err <= 1e-4)
         dec.close()
+
+
+def test_run_graph_replays_equal_direct_launches(pk):
+    """mbbp_run replays one captured graph per batch size; every replay (with eager work
+    and synchronisations in between) gives the counters of direct launches."""
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    shots = 3000
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
+    calls = [(1, 0.05, 0), (2, 0.08, 123), (3, 0.03, 10**7), (1, 0.05, 0)]
+    direct = []
+    dec.set_graph(False)
+    for seed, p, shot0 in calls:
+        direct.append(dec.run(seed, p, shot0, shots).cpu().numpy())
+    dec.set_graph(True)
+    for rep in range(2):
+        for (seed, p, shot0), ref in zip(calls, direct):
+            say(f"graph replay {rep} seed={seed} p={p} shot0={shot0}")
+            junk = torch.randn(1000, device="cuda").sum()   # eager work between replays
+            got = dec.run(seed, p, shot0, shots).cpu().numpy()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(got, ref)
+            assert float(junk) == float(junk)
+    # accumulation into the caller's counters
+    acc = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
+    dec.run(1, 0.05, 0, shots, acc)
+    dec.run(2, 0.08, 123, shots, acc)
+    np.testing.assert_array_equal(acc.cpu().numpy(), direct[0] + direct[1])
+    dec.close()
+
+
+def test_autotune_keeps_results(pk):
+    wl = WORKLOADS["bb144_L16_T50"]
+    code = wl.code()
+    shots = 4000
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
+    ex, ez, sx, sz = dec.sample(5, 0.06, 0, shots)
+    prior = torch.full((code.n,), f32(oracle.prior_llr(0.06)), dtype=torch.float32, device="cuda")
+    before = dec.decode_batched(sx, sz, prior, prior)
+    b0 = {k: v.cpu().numpy() for k, v in before.items()}
+    for form in (0, 1):
+        cfg = dec.autotune(form, seed=9, p=0.05, shots=shots)
+        say(f"autotune form {form}: {cfg}")
+        assert cfg == dec.get_config(form)
+    after = dec.decode_batched(sx, sz, prior, prior)
+    plain = dec.decode(sx, sz, prior, prior)
+    torch.cuda.synchronize()
+    for k in b0:
+        np.testing.assert_array_equal(after[k].cpu().numpy(), b0[k], err_msg=k)
+        np.testing.assert_array_equal(plain[k].cpu().numpy(), b0[k], err_msg=k)
+    dec.close()
