@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--wpb", type=int, default=4, help="waves per block (with --lpi)")
     ap.add_argument("--chunk", type=int, default=8, help="shots per work item (with --lpi)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-shots", type=int, default=1500, help="oracle sample: shots per error rate")
+    ap.add_argument("--cpu-shots", type=int, default=20000, help="oracle sample: shots per error rate")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
