@@ -49,11 +49,34 @@ def parse():
     ap.add_argument("--wpb", type=int, default=4, help="waves per block (with --lpi)")
     ap.add_argument("--chunk", type=int, default=8, help="shots per work item (with --lpi)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-shots", type=int, default=20000, help="oracle sample: shots per error rate")
+    ap.add_argument("--cpu-shots", type=int, default=60000, help="oracle sample: shots per error rate")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
+
+
+def recorded_traffic(workload, shots_per_launch):
+    """HBM bytes per BP launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when that summary was taken on another BP kernel source or
+    another launch size."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"bp_wave_kernel_{workload}.md")
+    src = os.path.join(ROOT, "paper_2605_14170_amd", "csrc", "mbbp_bp.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            key, _, val = line.partition(":")
+            fields[key.strip()] = val.split()[0] if val.split() else ""
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha256") != sha or int(fields.get("shots_per_launch", -1)) != shots_per_launch:
+            return None
+        return float(fields["bp_kernel_hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def build_decoder(pk, wl, code, max_batch):
@@ -165,7 +188,8 @@ def main():
     edges_per_launch = edges / max(1, bp_launches)
     achieved = edges_per_launch * OPS_PER_EDGE_UPDATE / bp_avg_s / 1e12 if bp_launches else None
     roofline = dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="T lane-op/s",
-                    frac=(achieved / VALU_PEAK_TOPS) if achieved else None, traffic=None,
+                    frac=(achieved / VALU_PEAK_TOPS) if achieved else None, traffic_unit="B per launch",
+                    traffic=recorded_traffic(wl.key, shots) if args.form == "batched" else None,
                     kernel="bp_kernel", avg_launch_ms=bp_avg_s * 1e3,
                     edge_updates_per_launch=edges_per_launch,
                     ops_per_edge_update=OPS_PER_EDGE_UPDATE)

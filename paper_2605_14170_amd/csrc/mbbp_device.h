@@ -110,6 +110,7 @@ struct SelectArgs {
     DevPart part[2];
     int part0, nparts;
     int rule;                // 0 least weight, 1 FWS
+    int group;               // lanes per (part, shot); set by launch_select
     int64_t shots;
     const uint64_t *cand[2];
     const uint16_t *kstat[2];
@@ -140,7 +141,7 @@ struct BPConfig {
 
 hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
-hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_select(SelectArgs a, hipStream_t s);
 hipError_t launch_fail(const FailArgs &a, hipStream_t s);
 hipError_t launch_reset(unsigned long long *queue, int64_t *counters, int ncounters, hipStream_t s);
 // Per-run preparation: descriptor stored, uniform priors mu for both parts, per-shot
