@@ -27,7 +27,7 @@ _LIBS: Dict[str, ctypes.CDLL] = {}
 ORC_OK, ORC_EINVAL, ORC_ENOTINROWSPACE, ORC_ENOMEM = 0, -1, -2, -3
 
 FLOODING, LAYERED = 0, 1
-NMS, SPA = 0, 1
+NMS, SPA, WNMS = 0, 1, 2
 MIN_WEIGHT, FWS = 0, 1
 
 
@@ -72,7 +72,7 @@ def _declare(lib: ctypes.CDLL) -> None:
     lib.orc_subtrees.argtypes = [i32, i32, _P, _P, _P, _P, _P, _P]
     lib.orc_build_bases.argtypes = [i32, i32, _P, _P, i32, i32, i32, _P, _P, _P, i32]
     lib.orc_decode.argtypes = [i32, i32, _P, _P, i32, _P, _P, _P, i32, i32, i32, dbl, dbl, i32,
-                               i64, _P, i32, _P, _P, _P, _P, _P, _P, _P, i32, _P, _P]
+                               i64, _P, i32, _P, _P, _P, _P, _P, _P, _P, i32, _P, _P, _P, _P]
     lib.orc_failures.argtypes = [i32, i32, _P, _P, i64, _P, _P, _P]
     lib.orc_in_rowspace.argtypes = [i32, i32, _P, _P, i32, _P, _P, _P]
     lib.orc_real_bytes.argtypes = []
@@ -224,7 +224,12 @@ def decode(h: np.ndarray, basis_ptr: np.ndarray, rows: np.ndarray, syn: np.ndarr
            prior: np.ndarray, T: int, schedule: int = FLOODING, rule: int = NMS,
            alpha: float = 0.875, rmax: float = 65536.0, fixed_T: bool = False,
            select_rule: int = MIN_WEIGHT, want_llr: bool = False, precision: str = "f64",
-           explicit: Optional[Dict[int, np.ndarray]] = None) -> DecodeResult:
+           explicit: Optional[Dict[int, np.ndarray]] = None,
+           walpha: Optional[np.ndarray] = None, wbeta: Optional[np.ndarray] = None) -> DecodeResult:
+    """BP on every representation and the list decision (Algorithm 1).  rule WNMS
+    is the weighted min-sum with damping; walpha, wbeta are [T][L] (iteration t at
+    row t - 1) and margin[..., 0] is then the distance to the nearest non-smooth
+    point of the forward map."""
     lib = _lib(precision)
     m, n = h.shape
     ptr, idx = csr(h)
@@ -244,11 +249,15 @@ def decode(h: np.ndarray, basis_ptr: np.ndarray, rows: np.ndarray, syn: np.ndarr
     clamp = np.zeros((shots, L), np.uint8)
     chosen = np.zeros(shots, np.int32)
     corr = np.zeros((shots, wn), np.uint64)
+    wa = wb = None
+    if rule == WNMS:
+        wa = np.ascontiguousarray(walpha, np.float64).reshape(int(T), L)
+        wb = np.ascontiguousarray(wbeta, np.float64).reshape(int(T), L)
     _check(lib.orc_decode(m, n, _ptr(ptr), _ptr(idx), L, _ptr(bp), _ptr(ap), _ptr(ai),
                           int(T), int(schedule), int(rule), float(alpha), float(rmax),
                           1 if fixed_T else 0, shots, _ptr(prior), per_shot, _ptr(syn),
                           _ptr(cand), _ptr(K), _ptr(conv), _ptr(llr), _ptr(margin), _ptr(clamp),
-                          int(select_rule), _ptr(chosen), _ptr(corr)), "decode")
+                          int(select_rule), _ptr(chosen), _ptr(corr), _ptr(wa), _ptr(wb)), "decode")
     return DecodeResult(cand, K, conv.astype(bool), llr, margin, clamp.astype(bool), chosen, corr)
 
 

@@ -18,6 +18,11 @@
  *                         min-sum, flooding or serial schedule; sum-product as the
  *                         textbook tanh rule) and the list decision (Algorithm 1,
  *                         Section III-B: least weight, or FWS)
+ *   - weighted min-sum  : the differentiable form of the decoder (not in the paper):
+ *                         per-iteration, per-representation scaling alpha_{t,l} and
+ *                         damping beta_{t,l} of the min-sum check message,
+ *                         r^(t) = clamp((1 - beta) * S * alpha * M + beta * r^(t-1)),
+ *                         r^(0) = 0 (rule 2 of orc_decode, flooding only)
  *   - orc_failures      : logical failure = residual not a stabilizer (Section II-A)
  *   - orc_philox4x64_10 / orc_sample : counter-based depolarizing noise (Philox,
  *                         Salmon et al., SC'11), syndromes s = H e
@@ -467,6 +472,37 @@ static real nms_msg(const real *qin, int d, int skip, int sbit, real alpha, real
     return clampr(r, rmax, hit);
 }
 
+/* Weighted normalized min-sum with damping: the message is
+ * clamp((1 - beta) * v + beta * rprev) with v = S * (alpha * M), S the
+ * syndrome-signed product of the other slots' signs and M the smallest magnitude
+ * among them; rprev is the same edge's message of the previous iteration.
+ * *kink receives the smallest distance seen from a point where this map is not
+ * smooth: a sign change (|q| = 0), a change of the minimizing slot (the gap
+ * between the two smallest magnitudes among the other slots) or the clamp bound.
+ * The first two count only when the incoming messages depend on the weights
+ * (qvar != 0, i.e. from iteration 2 on; at iteration 1 they are the priors).  */
+static real wnms_msg(const real *qin, int d, int skip, int sbit, real alpha, real beta, real rprev, real rmax,
+                     int qvar, int *hit, double *kink) {
+    real mn = (real)INFINITY, mn2 = (real)INFINITY;
+    int neg = sbit;
+    for (int k = 0; k < d; ++k) {
+        if (k == skip) continue;
+        real a = qin[k] < 0 ? -qin[k] : qin[k];
+        if (qvar && (double)a < *kink) *kink = (double)a;
+        if (a < mn) { mn2 = mn; mn = a; }
+        else if (a < mn2) mn2 = a;
+        if (qin[k] < 0) neg ^= 1;
+    }
+    if (qvar && d > 2 && (double)mn2 - (double)mn < *kink) *kink = (double)mn2 - (double)mn;
+    real u = alpha * mn;
+    real v = neg ? -u : u;
+    real keep = (real)1 - beta;
+    real wsum = keep * v + beta * rprev;
+    double dist = fabs(fabs((double)wsum) - (double)rmax);
+    if (dist < *kink) *kink = dist;
+    return clampr(wsum, rmax, hit);
+}
+
 /* phi(x) = ln((e^x + 1) / (e^x - 1)), its own inverse; phi(0) = inf, phi(inf) = 0 */
 static real phi(real x) {
     if (x <= 0) return (real)INFINITY;
@@ -495,7 +531,9 @@ static real spa_msg(const real *qin, int d, int skip, int sbit, real rmax, int *
 
 /* ------------------------------------------------------------------------- */
 /* BP on one representation for one syndrome.
- * schedule: 0 flooding, 1 serial (layered).  rule: 0 normalized min-sum, 1 sum-product.
+ * schedule: 0 flooding, 1 serial (layered).  rule: 0 normalized min-sum, 1 sum-product,
+ * 2 weighted min-sum with damping (flooding only; wa[t-1], wb[t-1] are the weights
+ * of iteration t).
  * fixed_T: run exactly T iterations (diagnostic); *K then holds the first
  * iteration at which the syndrome was met (T if never) and dec/P the state after T. */
 
@@ -514,7 +552,7 @@ static int syndrome_met(const aug_graph *g, const uint8_t *dec, const uint8_t *s
 }
 
 static void bp_one(const aug_graph *g, const uint8_t *sb, const real *mu, int T, int schedule, int rule,
-                   real alpha, real rmax, int fixed_T, bp_work *w,
+                   real alpha, real rmax, int fixed_T, const real *wa, const real *wb, bp_work *w,
                    int *K_out, int *conv_out, double *m_sign, double *m_dec, int *clamp_hit) {
     const int n = g->n, M = g->M;
     double msign = INFINITY, mdec = INFINITY;
@@ -535,9 +573,11 @@ static void bp_one(const aug_graph *g, const uint8_t *sb, const real *mu, int T,
                     int d = g->cptr[j + 1] - g->cptr[j];
                     for (int k = 0; k < d; ++k) w->qin[k] = w->q[g->cptr[j] + k];
                     for (int k = 0; k < d; ++k) {
-                        w->r[g->cptr[j] + k] = rule == 0
-                            ? nms_msg(w->qin, d, k, sb[j], alpha, rmax, &hit, &msign)
-                            : spa_msg(w->qin, d, k, sb[j], rmax, &hit, &msign);
+                        real *re = &w->r[g->cptr[j] + k];
+                        *re = rule == 0 ? nms_msg(w->qin, d, k, sb[j], alpha, rmax, &hit, &msign)
+                            : rule == 1 ? spa_msg(w->qin, d, k, sb[j], rmax, &hit, &msign)
+                                        : wnms_msg(w->qin, d, k, sb[j], wa[t - 1], wb[t - 1], *re, rmax, t > 1,
+                                                   &hit, &msign);
                     }
                 }
                 /* variables: posterior and exclusion sums, ascending check order */
@@ -650,16 +690,20 @@ static int select_one(int L, int wn, const uint64_t *cand, const uint8_t *conv, 
  *   margin [shots][L][2]           min |q| at sign evaluations, min |P| at decisions
  *   clamp  [shots][L]              1 if the clamp bound
  *   chosen [shots]                 selected basis or -1
- *   corr   [shots][ceil(n/64)]     selected correction                          */
+ *   corr   [shots][ceil(n/64)]     selected correction
+ * Rule 2 (weighted min-sum) takes walpha, wbeta [T][L] (iteration t = 1..T at row
+ * t - 1) and reports in margin[0] the distance to the nearest non-smooth point of
+ * the forward map instead of the smallest |q|.                                  */
 
 int orc_decode(int m, int n, const int *row_ptr, const int *col_idx,
                int L, const int *basis_ptr, const int *app_ptr, const int *app_idx,
                int T, int schedule, int rule, double alpha, double rmax, int fixed_T,
                int64_t shots, const double *prior, int prior_per_shot, const uint64_t *syn,
                uint64_t *cand, int32_t *K, uint8_t *conv, double *llr, double *margin, uint8_t *clamp,
-               int select_rule, int32_t *chosen, uint64_t *corr) {
+               int select_rule, int32_t *chosen, uint64_t *corr, const double *walpha, const double *wbeta) {
     if (m <= 0 || n <= 0 || L <= 0 || T < 0 || shots < 0) return ORC_EINVAL;
-    if (schedule < 0 || schedule > 1 || rule < 0 || rule > 1) return ORC_EINVAL;
+    if (schedule < 0 || schedule > 1 || rule < 0 || rule > 2) return ORC_EINVAL;
+    if (rule == 2 && (schedule != 0 || !walpha || !wbeta)) return ORC_EINVAL;
     for (int j = 0; j < m; ++j)
         if (row_ptr[j + 1] - row_ptr[j] < 2) return ORC_EINVAL;
     gf2_basis hb;
@@ -693,7 +737,10 @@ int orc_decode(int m, int n, const int *row_ptr, const int *col_idx,
     uint8_t *sb = (uint8_t *)malloc((size_t)(maxM + 1));
     uint64_t *cl = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)L * (size_t)wn);
     uint8_t *cv = (uint8_t *)malloc((size_t)L);
-    if (!w.q || !w.r || !w.P || !w.qin || !w.rout || !w.dec || !mu || !sb || !cl || !cv) status = ORC_ENOMEM;
+    real *wa = (real *)malloc(sizeof(real) * (size_t)(T + 1));
+    real *wb = (real *)malloc(sizeof(real) * (size_t)(T + 1));
+    if (!w.q || !w.r || !w.P || !w.qin || !w.rout || !w.dec || !mu || !sb || !cl || !cv || !wa || !wb)
+        status = ORC_ENOMEM;
     const real ralpha = (real)alpha, rrmax = (real)rmax;
     for (int64_t s = 0; s < shots && status == ORC_OK; ++s) {
         const double *pr = prior + (prior_per_shot ? (size_t)s * n : 0);
@@ -709,9 +756,14 @@ int orc_decode(int m, int n, const int *row_ptr, const int *col_idx,
                     if (getbit(cb, j)) par ^= sb[j];
                 sb[m + a] = (uint8_t)par;
             }
+            if (rule == 2)
+                for (int t = 0; t < T; ++t) {
+                    wa[t] = (real)walpha[(size_t)t * L + l];
+                    wb[t] = (real)wbeta[(size_t)t * L + l];
+                }
             int k = 0, c = 0, hit = 0;
             double ms = 0, md = 0;
-            bp_one(gl, sb, mu, T, schedule, rule, ralpha, rrmax, fixed_T, &w, &k, &c, &ms, &md, &hit);
+            bp_one(gl, sb, mu, T, schedule, rule, ralpha, rrmax, fixed_T, wa, wb, &w, &k, &c, &ms, &md, &hit);
             uint64_t *cw = cl + (size_t)l * wn;
             memset(cw, 0, sizeof(uint64_t) * (size_t)wn);
             for (int i = 0; i < n; ++i)
@@ -733,7 +785,7 @@ int orc_decode(int m, int n, const int *row_ptr, const int *col_idx,
         else memset(co, 0, sizeof(uint64_t) * (size_t)wn);
     }
     free(w.q); free(w.r); free(w.P); free(w.qin); free(w.rout); free(w.dec);
-    free(mu); free(sb); free(cl); free(cv);
+    free(mu); free(sb); free(cl); free(cv); free(wa); free(wb);
     for (int l = 0; l < L; ++l) aug_free(&g[l]);
     free(g);
     gf2_free(&hb);
