@@ -53,7 +53,8 @@ typedef enum {
 } mbbp_status;
 
 typedef enum { MBBP_FLOODING = 0, MBBP_LAYERED = 1 } mbbp_schedule;  /* Section II-B */
-typedef enum { MBBP_NMS = 0, MBBP_SPA = 1 } mbbp_rule;              /* eq. (1) / tanh rule */
+/* eq. (1) / tanh rule / weighted min-sum with damping (see mbbp_set_weights) */
+typedef enum { MBBP_NMS = 0, MBBP_SPA = 1, MBBP_WEIGHTED = 2 } mbbp_rule;
 typedef enum { MBBP_MIN_WEIGHT = 0, MBBP_FWS = 1 } mbbp_select_rule; /* Section III-B */
 typedef enum { MBBP_PART_X = 0, MBBP_PART_Z = 1 } mbbp_part;
 
@@ -85,7 +86,7 @@ typedef struct {
 #define MBBP_FLAG_FIXED_T 1u  /* diagnostic: run exactly T iterations, no early stop */
 
 typedef struct {
-    int32_t rule;        /* mbbp_rule, default MBBP_NMS */
+    int32_t rule;        /* mbbp_rule, default MBBP_NMS; MBBP_WEIGHTED needs MBBP_FLOODING */
     float alpha;         /* normalisation of eq. (1), default 0.875 (Section IV); unused by SPA */
     float r_max;         /* check messages are clamped to [-r_max, r_max], default 65536 */
     int32_t select;      /* mbbp_select_rule, default MBBP_MIN_WEIGHT */
@@ -243,6 +244,59 @@ mbbp_status mbbp_edge_counts(mbbp_ctx *ctx, int32_t part, int64_t *edges);
 
 /* Message for the last non-OK status returned on this thread. */
 const char *mbbp_last_error(void);
+
+/* ---- Weighted (differentiable) form of the decoder ------------------------------
+ * Not part of the paper's method: a learned variant of its normalized min-sum
+ * (eq. (1)) with a scaling alpha_{t,l} and a damping beta_{t,l} per iteration t and
+ * representation l, flooding schedule:
+ *   r^(t) = clamp((1 - beta_{t,l}) * S * (alpha_{t,l} * M) + beta_{t,l} * r^(t-1)),
+ *   r^(0) = 0, M the smallest |q| over the row's other edges, S the product of
+ *   their signs and of (-1)^{s_j}; variables as eq. (2).  beta = 0 and a constant
+ *   alpha give plain normalized min-sum bit for bit.
+ * Weights are device float arrays [T][L] (iteration t at row t - 1), shared by
+ * both parts (representation l of H_Z and of H_X use column l); both parts must
+ * have the same L. */
+
+/* Weights used by decode / decode_batched / decode_detail / run when the context
+ * was created with rule MBBP_WEIGHTED.  Device pointers, read at every launch
+ * (their contents may change between calls; the pointers must stay valid).
+ * Pass NULL, NULL to clear.  Decoding with MBBP_WEIGHTED and no weights is
+ * MBBP_EINVAL.  Changing the pointers drops captured mbbp_run graphs. */
+mbbp_status mbbp_set_weights(mbbp_ctx *ctx, const float *alpha, const float *beta);
+
+/* Floats of the checkpoint buffer of mbbp_wbp_forward for `shots` shots of one part
+ * with a checkpoint every ckpt_every >= 1 iterations:
+ * shots * L * (ceil(T / ckpt_every) - 1) * 8 * Mpad, Mpad the kernel's padded row
+ * count for that part. */
+mbbp_status mbbp_wbp_ckpt_floats(mbbp_ctx *ctx, int32_t part, int64_t shots, int32_t ckpt_every, int64_t *floats);
+
+/* Training forward of one part: weighted min-sum for exactly T iterations (no early
+ * stop) on every representation, any rule the context was created with.
+ * syn, prior as in mbbp_decode_detail; alpha, beta device [T][L].
+ * llr  device float [shots][L][n]: the posterior P^(T) of every representation.
+ * ckpt device float [mbbp_wbp_ckpt_floats]: c->v messages r^(t) for t = ckpt_every,
+ *      2 ckpt_every, ... < T (may be NULL when that list is empty); opaque layout,
+ *      read by mbbp_wbp_backward with the same arguments.
+ * Candidates and iteration counts go to the context's workspace (overwritten). */
+mbbp_status mbbp_wbp_forward(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn, const float *prior,
+                             int32_t prior_per_shot, const float *alpha, const float *beta, int32_t ckpt_every,
+                             float *ckpt, float *llr, void *hip_stream);
+
+/* Adjoint of mbbp_wbp_forward: given grad_llr = dL/dP^(T) (device float
+ * [shots][L][n]), ADDS dL/dalpha and dL/dbeta (device float [T][L]) into grad_alpha,
+ * grad_beta.  Same syn, prior, alpha, beta, ckpt_every and ckpt as the forward.
+ * Each segment of ckpt_every iterations is recomputed from its checkpoint, so the
+ * result does not depend on ckpt_every.  Subgradients: the minimum passes its
+ * adjoint to the first edge (in row order) of smallest magnitude among the others,
+ * d|x|/dx = sign of x, sign factors are constant, the clamp passes the adjoint only
+ * strictly inside (-r_max, r_max).  Per-instance partial sums are added over shots
+ * in FP64 in a fixed order: results are deterministic.
+ * Limits (MBBP_EUNSUPPORTED): n <= 320 and at most 319 checks per representation;
+ * (3 + ckpt_every) * 32 * Mpad bytes of LDS per instance must fit 64 KiB. */
+mbbp_status mbbp_wbp_backward(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn, const float *prior,
+                              int32_t prior_per_shot, const float *alpha, const float *beta, int32_t ckpt_every,
+                              const float *ckpt, const float *grad_llr, float *grad_alpha, float *grad_beta,
+                              void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import MbbpError, NUM_COUNTERS  # noqa: F401
 
 FLOODING, LAYERED = 0, 1
-NMS, SPA = 0, 1
+NMS, SPA, WEIGHTED = 0, 1, 2
 MIN_WEIGHT, FWS = 0, 1
 PART_X, PART_Z = 0, 1
 
@@ -273,6 +273,68 @@ class Decoder:
         _lib.check(_lib.lib().mbbp_bp_time(self._ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0),
                    "mbbp_bp_time")
         return ms.value, n.value
+
+    # ------------------------------------------------------------------ weighted form
+    def set_weights(self, alpha, beta) -> None:
+        """Weights [T, L] (device float32) for decoding with rule WEIGHTED; None, None
+        clears.  The tensors are kept referenced while set."""
+        torch = _torch()
+        if alpha is None and beta is None:
+            _lib.check(_lib.lib().mbbp_set_weights(self._ctx, None, None), "mbbp_set_weights")
+            self._weights = None
+            return
+        _need(alpha, "alpha", (self.T, self.L), torch.float32)
+        _need(beta, "beta", (self.T, self.L), torch.float32)
+        _lib.check(_lib.lib().mbbp_set_weights(self._ctx, _ptr(alpha), _ptr(beta)), "mbbp_set_weights")
+        self._weights = (alpha, beta)
+
+    def _wbp_check(self, part, syn, prior, alpha, beta):
+        torch = _torch()
+        shots = int(syn.shape[0])
+        m = self.mz if int(part) == 0 else self.mx
+        _need(syn, "syn", (shots, (m + 63) // 64), torch.int64)
+        _need(prior, "prior", _prior_shape(prior, shots, self.n), torch.float32)
+        _need(alpha, "alpha", (self.T, self.L), torch.float32)
+        _need(beta, "beta", (self.T, self.L), torch.float32)
+        return shots, (1 if prior.dim() == 2 else 0)
+
+    def wbp_ckpt_floats(self, part: int, shots: int, ckpt_every: int) -> int:
+        n = ctypes.c_int64()
+        _lib.check(_lib.lib().mbbp_wbp_ckpt_floats(self._ctx, int(part), int(shots), int(ckpt_every),
+                                                   ctypes.byref(n)), "mbbp_wbp_ckpt_floats")
+        return int(n.value)
+
+    def wbp_forward(self, part: int, syn, prior, alpha, beta, ckpt_every: int = 5, stream=None):
+        """Weighted min-sum for exactly T iterations on every representation of one
+        part: (P^(T) [shots, L, n] float32, checkpoint buffer for wbp_backward)."""
+        torch = _torch()
+        shots, pps = self._wbp_check(part, syn, prior, alpha, beta)
+        llr = self._dev((shots, self.L, self.n), torch.float32)
+        nck = self.wbp_ckpt_floats(part, shots, ckpt_every)
+        ckpt = self._dev((max(nck, 1),), torch.float32)
+        _lib.check(_lib.lib().mbbp_wbp_forward(self._ctx, int(part), shots, _ptr(syn), _ptr(prior), pps,
+                                               _ptr(alpha), _ptr(beta), int(ckpt_every), _ptr(ckpt), _ptr(llr),
+                                               _stream(stream)), "mbbp_wbp_forward")
+        return llr, ckpt
+
+    def wbp_backward(self, part: int, syn, prior, alpha, beta, ckpt_every: int, ckpt, grad_llr,
+                     grad_alpha=None, grad_beta=None, stream=None):
+        """Adds dL/dalpha, dL/dbeta ([T, L] float32) of one part, given dL/dP^(T)."""
+        torch = _torch()
+        shots, pps = self._wbp_check(part, syn, prior, alpha, beta)
+        _need(grad_llr, "grad_llr", (shots, self.L, self.n), torch.float32)
+        if grad_alpha is None:
+            grad_alpha = torch.zeros((self.T, self.L), dtype=torch.float32, device="cuda")
+        if grad_beta is None:
+            grad_beta = torch.zeros((self.T, self.L), dtype=torch.float32, device="cuda")
+        _need(grad_alpha, "grad_alpha", (self.T, self.L), torch.float32)
+        _need(grad_beta, "grad_beta", (self.T, self.L), torch.float32)
+        _need(ckpt, "ckpt", (max(self.wbp_ckpt_floats(part, shots, ckpt_every), 1),), torch.float32)
+        _lib.check(_lib.lib().mbbp_wbp_backward(self._ctx, int(part), shots, _ptr(syn), _ptr(prior), pps,
+                                                _ptr(alpha), _ptr(beta), int(ckpt_every), _ptr(ckpt),
+                                                _ptr(grad_llr), _ptr(grad_alpha), _ptr(grad_beta),
+                                                _stream(stream)), "mbbp_wbp_backward")
+        return grad_alpha, grad_beta
 
     def run(self, seed: int, p: float, shot0: int, shots: int, counters=None, stream=None):
         torch = _torch()

@@ -18,73 +18,11 @@
 // Phases are wave-synchronous: no workgroup barrier is ever needed.
 #include <hip/hip_runtime.h>
 
+#include "mbbp_bp_rules.h"
 #include "mbbp_device.h"
 #include "mbbp_wave.h"
 
 namespace mbbp {
-
-template <int RULE>
-struct CheckRule;
-
-// Normalized min-sum (eq. (1)) with syndrome sign and clamp: the message to slot k
-// is (-1)^{s_j} * prod_{k' != k} sgn(q_k') * min(alpha * min_{k' != k} |q_k'|, rmax).
-// min over the others is min2 for the (first) minimum and min1 for every other slot.
-template <>
-struct CheckRule<0> {
-    template <int DC>
-    __device__ __forceinline__ static void apply(float (&q)[DC], int sbit, float alpha, float rmax) {
-        float m1 = fminf(fabsf(q[0]), fabsf(q[1]));
-        float m2 = fmaxf(fabsf(q[0]), fabsf(q[1]));
-        uint32_t sx = fbits(q[0]) ^ fbits(q[1]);
-#pragma unroll
-        for (int k = 2; k < DC; ++k) {
-            const float a = fabsf(q[k]);
-            m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
-            m1 = fminf(m1, a);
-            sx ^= fbits(q[k]);
-        }
-        const float A1 = fminf(alpha * m1, rmax);
-        const float A2 = fminf(alpha * m2, rmax);
-        const uint32_t sgn = (sx & 0x80000000u) ^ ((uint32_t)sbit << 31);
-#pragma unroll
-        for (int k = 0; k < DC; ++k) {
-            const float mag = (fabsf(q[k]) == m1) ? A2 : A1;
-            q[k] = bitsf(fbits(mag) | ((fbits(q[k]) ^ sgn) & 0x80000000u));
-        }
-    }
-};
-
-// Sum-product: pairwise box-plus x [+] y = sgn(x) sgn(y) min(|x|,|y|)
-//   + log(1 + e^{-|x+y|}) - log(1 + e^{-|x-y|}), forward/backward over the row so
-// slot k gets the box-plus of all other slots; syndrome sign; clamp.
-template <>
-struct CheckRule<1> {
-    __device__ __forceinline__ static float boxplus(float x, float y) {
-        const float ax = fabsf(x), ay = fabsf(y);
-        const float mn = fminf(ax, ay);
-        const float s = (fbits(x) ^ fbits(y)) & 0x80000000u ? -1.0f : 1.0f;
-        const float c1 = __logf(1.0f + __expf(-fabsf(x + y)));
-        const float c2 = __logf(1.0f + __expf(-fabsf(x - y)));
-        return s * mn + c1 - c2;
-    }
-    template <int DC>
-    __device__ __forceinline__ static void apply(float (&q)[DC], int sbit, float, float rmax) {
-        float f[DC], b[DC];
-        f[0] = q[0];
-#pragma unroll
-        for (int k = 1; k < DC; ++k) f[k] = boxplus(f[k - 1], q[k]);
-        b[DC - 1] = q[DC - 1];
-#pragma unroll
-        for (int k = DC - 2; k >= 0; --k) b[k] = boxplus(b[k + 1], q[k]);
-        const uint32_t sgn = (uint32_t)sbit << 31;
-#pragma unroll
-        for (int k = 0; k < DC; ++k) {
-            float r = (k == 0) ? b[1] : (k == DC - 1) ? f[DC - 2] : boxplus(f[k - 1], b[k + 1]);
-            r = fminf(fmaxf(r, -rmax), rmax);
-            q[k] = bitsf(fbits(r) ^ sgn);
-        }
-    }
-};
 
 struct ItemPos {
     int part, l;
@@ -108,67 +46,6 @@ __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 
 
 
 
-// LDS layout of one BP instance, 64 * PC rows (Mpad) of at most 8 edge slots:
-//   messages  float [8][Mpad]  slot-major: edge (j, k) at k * Mpad + j
-//   decisions u8    [8][Mpad]  stored as 32-bit cells at the message offset + 32 * Mpad,
-//                              so one table address serves both arrays
-//   syndrome words, output staging words, per-shot priors.
-// Rows >= M_l are unused by representation l; row Mmax (of the part) is the sink
-// of absent edges.  Every table entry is a byte address in LDS.
-template <int PC>
-struct Layout {
-    static constexpr int Mpad = 64 * PC;
-    static constexpr uint32_t kDecOff = 32u * Mpad;       // decisions after the messages
-    static constexpr uint32_t kTail = 64u * Mpad;         // syndrome words start here
-};
-
-// Variable rule (eq. (2) and the posterior of Section II-B) for a variable of
-// degree deg <= D (edges k >= deg point at the sink and read as 0):
-// P = mu + sum r,  q_k = mu + sum_{k' != k} r_k'  accumulated in ascending check
-// order (never P - r_k); every q_k and the hard decision are written back.
-template <int D, uint32_t DECOFF>
-__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
-    float r[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const float x = *lds_ptr_f32(ea[k]);
-        r[k] = k < deg ? x : 0.0f;
-    }
-    float q[D];
-    float pre = mu;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        float acc = pre;
-#pragma unroll
-        for (int k2 = k + 1; k2 < D; ++k2) acc += r[k2];
-        q[k] = acc;
-        pre += r[k];
-    }
-    dec = pre < 0.0f;
-    P = pre;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        *lds_ptr_f32(ea[k]) = q[k];
-        *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
-    }
-}
-
-// Posterior only (serial schedule): P = mu + sum r in ascending check order and the
-// hard decision written to every edge's decision cell; messages are left alone.
-template <int D, uint32_t DECOFF>
-__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
-    float pre = mu;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const float x = *lds_ptr_f32(ea[k]);
-        pre += k < deg ? x : 0.0f;
-    }
-    dec = pre < 0.0f;
-    P = pre;
-#pragma unroll
-    for (int k = 0; k < D; ++k) *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
-}
-
 // One instance per wavefront.  Every per-instance quantity (shot, iteration,
 // halting) is wave-uniform; per lane live only the variable slots' edge addresses,
 // priors and the check slots' syndrome bits.  Variable slots: s = v * 64 + lane,
@@ -182,9 +59,10 @@ __device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, 
 // over the conflict-free levels of the checks in which every check computes its
 // incoming messages from the latest check messages.
 template <int PV, int PC, int DC, int RULE, int SCHED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : 1)))
 void bp_wave_kernel(BPArgs a) {
-    using LY = Layout<PC>;
+    using LY = Layout<PC, RULE>;
+    static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
     constexpr int Mpad = LY::Mpad;
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -406,6 +284,15 @@ void bp_wave_kernel(BPArgs a) {
                 }
             } else {
                 while (true) {
+                    // ---------------- checkpoint of the c->v messages r^(it) (weighted, training)
+                    if constexpr (RULE == kRuleWeighted) {
+                        if (a.ckpt && it > 0 && it < T && it % a.ckpt_every == 0) {
+                            const uint4 *src = reinterpret_cast<const uint4 *>(ibase + LY::kROff);
+                            uint4 *dst = reinterpret_cast<uint4 *>(
+                                a.ckpt + (((size_t)shot * L + l) * a.n_ck + (it / a.ckpt_every - 1)) * (8 * Mpad));
+                            for (int i = lane; i < 2 * Mpad; i += 64) dst[i] = src[i];
+                        }
+                    }
                     // ---------------- variable phase
     #pragma unroll
                     for (int v = 0; v < PV; ++v) {
@@ -414,18 +301,18 @@ void bp_wave_kernel(BPArgs a) {
                             float Pv = 0.0f;
                             bool d = false;
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_rule<1, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 2: var_rule<2, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 3: var_rule<3, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 4: var_rule<4, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 5: var_rule<5, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 6: var_rule<6, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 7: var_rule<7, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 8: var_rule<8, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 1: var_rule<1, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 2: var_rule<2, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 3: var_rule<3, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 4: var_rule<4, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 5: var_rule<5, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 6: var_rule<6, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 7: var_rule<7, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 8: var_rule<8, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                            if (llr) {
+                            if (llr && (!a.fixed_T || it == T)) {
                                 const int s = v * 64 + lane;
                                 if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
                             }
@@ -435,6 +322,14 @@ void bp_wave_kernel(BPArgs a) {
                     // ---------------- check phase: syndrome test of the decisions, c->v messages.
                     // Rows beyond the representation's checks are junk rows (unused by it).
                     uint32_t unsat = 0;
+                    float w_alpha = 0.0f, w_beta = 0.0f, w_keep = 1.0f;
+                    if constexpr (RULE == kRuleWeighted) {
+                        if (it < T) {
+                            w_alpha = a.walpha[(size_t)it * L + l];
+                            w_beta = a.wbeta[(size_t)it * L + l];
+                            w_keep = 1.0f - w_beta;
+                        }
+                    }
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = c * 64 + lane;
@@ -454,9 +349,23 @@ void bp_wave_kernel(BPArgs a) {
                                 if (k >= w) q[k] = 3.402823466e38f;
                         }
                         unsat |= par & (j < Ml ? 1u : 0u);
-                        CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
+                        if constexpr (RULE == kRuleWeighted) {
+                            // c->v messages of iteration it + 1 (none after the last)
+                            if (it < T) {
+                                lds_f32 *rrow = lds_ptr_f32(ibase_addr + LY::kROff + 4u * (uint32_t)j);
+                                float rp[DC];
     #pragma unroll
-                        for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
+                                for (int k = 0; k < DC; ++k) rp[k] = rrow[k * Mpad];
+                                WeightedRule::apply<DC>(q, rp, (int)((sbits >> c) & 1u), w_alpha, w_keep, w_beta,
+                                                        rmax);
+    #pragma unroll
+                                for (int k = 0; k < DC; ++k) rrow[k * Mpad] = q[k];
+                            }
+                        } else {
+                            CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
+    #pragma unroll
+                            for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
+                        }
                     }
                     const bool sat = __ballot(unsat != 0u) == 0ull;
                     // ---------------- halting (Section II-B)
@@ -525,9 +434,20 @@ int bp_max_passes(int lpi) { return lpi == 64 ? 16 : 0; }
 
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule) {
     (void)dc_uniform;
-    if ((schedule != 0 && schedule != 1) || (rule != 0 && rule != 1) || lpi != 64) return false;
+    if ((schedule != 0 && schedule != 1) || rule < 0 || rule > 2 || lpi != 64) return false;
+    if (rule == kRuleWeighted && schedule != 0) return false;
     PassPair pp;
     return pick_pair(passes, passes, pp);
+}
+
+bool bp_passes(const BPArgs &a, int &pv, int &pc) {
+    int nv, nc;
+    passes_needed(a, nv, nc);
+    PassPair pp;
+    if (!pick_pair(nv, nc, pp)) return false;
+    pv = pp.pv;
+    pc = pp.pc;
+    return true;
 }
 
 bool bp_layout(const BPArgs &a, int &mpad) {
@@ -553,9 +473,16 @@ template <int PV, int PC, int SCHED>
 static hipError_t launch_pair(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
     bool u6 = true;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
-    if (rule == 0)
+    if (rule == kRuleNMS)
         return u6 ? launch_wave_t<PV, PC, 6, 0, SCHED>(a, cfg, s) : launch_wave_t<PV, PC, 8, 0, SCHED>(a, cfg, s);
-    return u6 ? launch_wave_t<PV, PC, 6, 1, SCHED>(a, cfg, s) : launch_wave_t<PV, PC, 8, 1, SCHED>(a, cfg, s);
+    if (rule == kRuleSPA)
+        return u6 ? launch_wave_t<PV, PC, 6, 1, SCHED>(a, cfg, s) : launch_wave_t<PV, PC, 8, 1, SCHED>(a, cfg, s);
+    if constexpr (SCHED == 0) {
+        if (rule == kRuleWeighted)
+            return u6 ? launch_wave_t<PV, PC, 6, kRuleWeighted, 0>(a, cfg, s)
+                      : launch_wave_t<PV, PC, 8, kRuleWeighted, 0>(a, cfg, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int SCHED>

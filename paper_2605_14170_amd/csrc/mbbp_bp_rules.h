@@ -1,0 +1,246 @@
+// Check and variable rules of the BP kernels (Section II-B, eqs. (1)-(2)) and the
+// LDS layout of one BP instance, shared by the decoding kernel and the adjoint
+// (backward) kernel of the weighted decoder, so a recomputed iteration is the
+// same arithmetic as the forward one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mbbp_device.h"
+#include "mbbp_wave.h"
+
+namespace mbbp {
+
+constexpr int kRuleNMS = 0, kRuleSPA = 1, kRuleWeighted = 2;
+
+template <int RULE>
+struct CheckRule;
+
+// Two smallest magnitudes of a row (m1 <= m2, equal on a tie) and the XOR of all
+// sign bits.
+template <int DC>
+__device__ __forceinline__ void row_min2(const float (&q)[DC], float &m1, float &m2, uint32_t &sx) {
+    m1 = fminf(fabsf(q[0]), fabsf(q[1]));
+    m2 = fmaxf(fabsf(q[0]), fabsf(q[1]));
+    sx = fbits(q[0]) ^ fbits(q[1]);
+#pragma unroll
+    for (int k = 2; k < DC; ++k) {
+        const float a = fabsf(q[k]);
+        m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
+        m1 = fminf(m1, a);
+        sx ^= fbits(q[k]);
+    }
+}
+
+// Normalized min-sum (eq. (1)) with syndrome sign and clamp: the message to slot k
+// is (-1)^{s_j} * prod_{k' != k} sgn(q_k') * min(alpha * min_{k' != k} |q_k'|, rmax).
+// min over the others is min2 for the (first) minimum and min1 for every other slot.
+template <>
+struct CheckRule<kRuleNMS> {
+    template <int DC>
+    __device__ __forceinline__ static void apply(float (&q)[DC], int sbit, float alpha, float rmax) {
+        float m1, m2;
+        uint32_t sx;
+        row_min2<DC>(q, m1, m2, sx);
+        const float A1 = fminf(alpha * m1, rmax);
+        const float A2 = fminf(alpha * m2, rmax);
+        const uint32_t sgn = (sx & 0x80000000u) ^ ((uint32_t)sbit << 31);
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const float mag = (fabsf(q[k]) == m1) ? A2 : A1;
+            q[k] = bitsf(fbits(mag) | ((fbits(q[k]) ^ sgn) & 0x80000000u));
+        }
+    }
+};
+
+// Sum-product: pairwise box-plus x [+] y = sgn(x) sgn(y) min(|x|,|y|)
+//   + log(1 + e^{-|x+y|}) - log(1 + e^{-|x-y|}), forward/backward over the row so
+// slot k gets the box-plus of all other slots; syndrome sign; clamp.
+template <>
+struct CheckRule<kRuleSPA> {
+    __device__ __forceinline__ static float boxplus(float x, float y) {
+        const float ax = fabsf(x), ay = fabsf(y);
+        const float mn = fminf(ax, ay);
+        const float s = (fbits(x) ^ fbits(y)) & 0x80000000u ? -1.0f : 1.0f;
+        const float c1 = __logf(1.0f + __expf(-fabsf(x + y)));
+        const float c2 = __logf(1.0f + __expf(-fabsf(x - y)));
+        return s * mn + c1 - c2;
+    }
+    template <int DC>
+    __device__ __forceinline__ static void apply(float (&q)[DC], int sbit, float, float rmax) {
+        float f[DC], b[DC];
+        f[0] = q[0];
+#pragma unroll
+        for (int k = 1; k < DC; ++k) f[k] = boxplus(f[k - 1], q[k]);
+        b[DC - 1] = q[DC - 1];
+#pragma unroll
+        for (int k = DC - 2; k >= 0; --k) b[k] = boxplus(b[k + 1], q[k]);
+        const uint32_t sgn = (uint32_t)sbit << 31;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            float r = (k == 0) ? b[1] : (k == DC - 1) ? f[DC - 2] : boxplus(f[k - 1], b[k + 1]);
+            r = fminf(fmaxf(r, -rmax), rmax);
+            q[k] = bitsf(fbits(r) ^ sgn);
+        }
+    }
+};
+
+// Weighted min-sum with damping (the differentiable form of the decoder):
+//   r_k = clamp((1 - beta) * v_k + beta * rprev_k),  v_k = S_k * (alpha * M_k),
+// M_k the smallest |q| over the row's other slots, S_k the product of their signs
+// and of (-1)^{s_j}; keep = 1 - beta is passed in, evaluated once per iteration.
+// With beta = 0 and a constant alpha the result equals normalized min-sum.
+struct WeightedRule {
+    template <int DC>
+    __device__ __forceinline__ static void apply(float (&q)[DC], const float (&rp)[DC], int sbit, float alpha,
+                                                 float keep, float beta, float rmax) {
+        float m1, m2;
+        uint32_t sx;
+        row_min2<DC>(q, m1, m2, sx);
+        const float u1 = alpha * m1, u2 = alpha * m2;
+        const uint32_t sgn = (sx & 0x80000000u) ^ ((uint32_t)sbit << 31);
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const float u = (fabsf(q[k]) == m1) ? u2 : u1;
+            const float v = bitsf(fbits(u) ^ ((fbits(q[k]) ^ sgn) & 0x80000000u));  // any sign of alpha
+            const float w = keep * v + beta * rp[k];
+            q[k] = fminf(fmaxf(w, -rmax), rmax);
+        }
+    }
+
+    // Adjoint of apply for one row.  In: q, rprev, the adjoint rb of the new
+    // messages (0 on unused slots).  Out: rb_prev[k] = the adjoint reaching rprev_k
+    // through the damping term, qb = the adjoint of q, and the row's contributions
+    // to dL/dalpha and dL/dbeta added to ga, gb.  Subgradients: the minimum passes
+    // its adjoint to the first slot (in row order) holding the smallest magnitude
+    // among the others, d|x|/dx follows the sign bit of x, sign factors are
+    // constant, the clamp passes the adjoint only strictly inside (-rmax, rmax).
+    template <int DC>
+    __device__ __forceinline__ static void adjoint(const float (&q)[DC], const float (&rp)[DC],
+                                                   const float (&rb)[DC], int sbit, float alpha, float keep,
+                                                   float beta, float rmax, float (&rb_prev)[DC], float (&qb)[DC],
+                                                   float &ga, float &gb) {
+        // i1: first slot of the smallest |q|; i2: first other slot of the smallest
+        // |q| among the rest.  Their values equal the forward's m1 and m2.
+        float m1 = fabsf(q[0]);
+        int i1 = 0;
+#pragma unroll
+        for (int k = 1; k < DC; ++k) {
+            const float a = fabsf(q[k]);
+            if (a < m1) { m1 = a; i1 = k; }
+        }
+        float m2 = 3.402823466e38f;
+        int i2 = i1 == 0 ? 1 : 0;
+        bool have = false;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const float a = fabsf(q[k]);
+            if (k != i1 && (!have || a < m2)) { m2 = a; i2 = k; have = true; }
+        }
+        uint32_t sx = 0;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) sx ^= fbits(q[k]);
+        const float u1 = alpha * m1, u2 = alpha * m2;
+        const uint32_t sgn = (sx & 0x80000000u) ^ ((uint32_t)sbit << 31);
+        float to_i1 = 0.0f, to_i2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const bool at1 = k == i1;
+            const float M = at1 ? m2 : m1;
+            const float u = at1 ? u2 : u1;
+            const uint32_t sk = (fbits(q[k]) ^ sgn) & 0x80000000u;  // sign of S_k
+            const float v = bitsf(fbits(u) ^ sk);
+            const float w = keep * v + beta * rp[k];
+            const float wb = (w > -rmax && w < rmax) ? rb[k] : 0.0f;
+            gb += wb * (rp[k] - v);
+            rb_prev[k] = wb * beta;
+            const float vb = wb * keep;
+            ga += vb * bitsf(fbits(M) ^ sk);
+            const float Mb = vb * bitsf(fbits(alpha) ^ sk);
+            if (at1) to_i2 += Mb;
+            else to_i1 += Mb;
+        }
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const float g = k == i1 ? to_i1 : (k == i2 ? to_i2 : 0.0f);
+            qb[k] = bitsf(fbits(g) ^ (fbits(q[k]) & 0x80000000u));
+        }
+    }
+};
+
+// LDS layout of one BP instance, 64 * PC rows (Mpad) of at most 8 edge slots:
+//   messages  float [8][Mpad]  slot-major: edge (j, k) at k * Mpad + j
+//   decisions u8    [8][Mpad]  stored as 32-bit cells at the message offset + 32 * Mpad,
+//                              so one table address serves both arrays
+//   weighted rule only: c->v messages float [8][Mpad] at + 64 * Mpad (the message
+//                              array then holds the v->c messages only)
+//   syndrome words, output staging words, per-shot priors.
+// Rows >= M_l are unused by representation l; row Mmax (of the part) is the sink
+// of absent edges.  Every table entry is a byte address in LDS.
+template <int PC, int RULE = kRuleNMS>
+struct Layout {
+    static constexpr int Mpad = 64 * PC;
+    static constexpr uint32_t kArr = 32u * Mpad;                            // bytes of one [8][Mpad] array
+    static constexpr uint32_t kDecOff = kArr;                               // decisions after the messages
+    static constexpr uint32_t kROff = RULE == kRuleWeighted ? 2u * kArr : 0u;  // where c->v messages live
+    static constexpr uint32_t kTail = (RULE == kRuleWeighted ? 3u : 2u) * kArr;  // syndrome words start here
+};
+
+// Exclusion sums of a variable of degree <= D with incoming messages r (unused
+// slots hold 0): q_k = mu + sum_{k' != k} r_k' and P = mu + sum r, both
+// accumulated in ascending check order (never P - r_k).
+template <int D>
+__device__ __forceinline__ float excl_sums(const float (&r)[D], float mu, float (&q)[D]) {
+    float pre = mu;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float acc = pre;
+#pragma unroll
+        for (int k2 = k + 1; k2 < D; ++k2) acc += r[k2];
+        q[k] = acc;
+        pre += r[k];
+    }
+    return pre;
+}
+
+// Variable rule (eq. (2) and the posterior of Section II-B) for a variable of
+// degree deg <= D (edges k >= deg point at the sink and read as 0): reads the c->v
+// messages at ea + ROFF, writes every q_k at ea and the hard decision at ea + DECOFF.
+template <int D, uint32_t DECOFF, uint32_t ROFF>
+__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
+    float r[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float x = *lds_ptr_f32(ea[k] + ROFF);
+        r[k] = k < deg ? x : 0.0f;
+    }
+    float q[D];
+    const float pre = excl_sums<D>(r, mu, q);
+    dec = pre < 0.0f;
+    P = pre;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        *lds_ptr_f32(ea[k]) = q[k];
+        *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+    }
+}
+
+// Posterior only (serial schedule): P = mu + sum r in ascending check order and the
+// hard decision written to every edge's decision cell; messages are left alone.
+template <int D, uint32_t DECOFF>
+__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
+    float pre = mu;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float x = *lds_ptr_f32(ea[k]);
+        pre += k < deg ? x : 0.0f;
+    }
+    dec = pre < 0.0f;
+    P = pre;
+#pragma unroll
+    for (int k = 0; k < D; ++k) *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+}
+
+}  // namespace mbbp

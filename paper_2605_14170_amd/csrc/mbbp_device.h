@@ -72,6 +72,12 @@ struct BPArgs {
     int zero_bytes;          // message rows + decision rows (cleared at every fill), multiple of 16
     int ws_max, w_max;       // syndrome words / candidate words of the launch's parts
     int n_max;               // priors staged in LDS (per-shot priors, serial schedule)
+    // weighted rule: alpha_{t,l}, beta_{t,l} as [T][L] (iteration t at row t - 1); with
+    // ckpt non-null the c->v messages r^(t) of t = ckpt_every, 2 ckpt_every, ... < T
+    // are stored per instance (shot * L + l) as n_ck arrays of 8 * Mpad floats
+    const float *walpha, *wbeta;
+    float *ckpt;
+    int ckpt_every, n_ck;
 };
 
 // Per-call parameters of the captured whole-path graph, written on device by the
@@ -140,6 +146,33 @@ struct BPConfig {
 };
 
 hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s);
+
+// Adjoint of the weighted decoder's fixed-T forward map for one part: per instance
+// (l, shot), segments of ckpt_every iterations are recomputed from the stored
+// checkpoints and run backwards; per-instance dL/dalpha_t, dL/dbeta_t go to partial.
+struct WBPBackArgs {
+    const DevPart *dpart;    // the part, in device memory
+    int L, T;
+    int64_t shots, n_items;  // n_items = L * shots, item = l * shots + shot
+    float rmax;
+    const uint64_t *syn;     // [shots][Ws]
+    const float *prior;      // [n] or [shots][n]
+    int prior_per_shot;
+    const float *walpha, *wbeta;  // [T][L]
+    const float *ckpt;       // [shots * L][n_ck][8 * Mpad]
+    int ckpt_every, n_ck;
+    const float *grad_llr;   // [shots][L][n]: dL/dP^(T)
+    float2 *partial;         // [T][n_items]: per-instance (dL/dalpha_t, dL/dbeta_t)
+    int inst_bytes, ws, n;
+};
+hipError_t launch_wbp_backward(const WBPBackArgs &a, int pv, int pc, int dc, int waves_per_block, hipStream_t s);
+// grad_alpha[t][l] += sum over shots of partial, likewise grad_beta (FP64 sums in a
+// fixed order, so results do not depend on scheduling).
+hipError_t launch_wbp_reduce(const float2 *partial, int64_t shots, int T, int L, float *grad_alpha,
+                             float *grad_beta, hipStream_t s);
+bool wbp_backward_supported(int pv, int pc);
+// (pv, pc) instantiation the BP kernel uses for the parts of a
+bool bp_passes(const BPArgs &a, int &pv, int &pc);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_select(SelectArgs a, hipStream_t s);
 hipError_t launch_fail(const FailArgs &a, hipStream_t s);

@@ -414,6 +414,11 @@ struct mbbp_ctx {
     mbbp::RunDesc *w_desc = nullptr;
     unsigned long long *w_queue = nullptr;
     int32_t *item_order = nullptr;
+    // weighted rule: user weights for decoding ([T][L] device floats, not owned)
+    const float *walpha = nullptr, *wbeta = nullptr;
+    // adjoint of the weighted decoder: per-instance gradient partials (grown on demand)
+    std::unique_ptr<DevBuf> gpart;
+    size_t gpart_bytes = 0;
     int cu_count = 256;
     mbbp::BPConfig plain_cfg{16, 4, 0, 0};
     mbbp::BPConfig batched_cfg{16, 4, 8, 0};
@@ -492,9 +497,11 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
 }
 
 // LDS bytes of one BP instance (must match bp_wave_kernel): messages and decision
-// cells for Mpad rows of 8 slots (64 * Mpad bytes), the syndrome words, the output
-// staging words and, for per-shot priors, the shot's n priors.
-bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, mbbp::BPArgs &a) {
+// cells for Mpad rows of 8 slots (64 * Mpad bytes; the weighted rule adds the c->v
+// messages, 32 * Mpad bytes), the syndrome words, the output staging words and, for
+// per-shot priors, the shot's n priors.
+bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, int rule,
+                 mbbp::BPArgs &a) {
     int W = 0, Ws = 0, n = 0;
     for (int p = part0; p < part0 + nparts; ++p) {
         W = std::max(W, c->dp[p].W);
@@ -510,7 +517,10 @@ bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, 
     a.zero_bytes = 64 * mpad;
     // serial schedule: priors always staged (n floats) plus one syndrome byte per row
     const bool serial = schedule == MBBP_LAYERED;
-    const int bytes = 64 * mpad + Ws * 8 + W * 8 + ((per_shot_prior || serial) ? n * 4 : 0) + (serial ? mpad : 0);
+    // the weighted rule keeps the c->v messages in a third [8][Mpad] array
+    const int arrays = rule == MBBP_WEIGHTED ? 3 : 2;
+    const int bytes = arrays * 32 * mpad + Ws * 8 + W * 8 + ((per_shot_prior || serial) ? n * 4 : 0) +
+                      (serial ? mpad : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     return true;
 }
@@ -538,9 +548,19 @@ mbbp_status check_stream_ptrs(const void *p, const char *what) {
     return MBBP_OK;
 }
 
+// Weighted-decoder training call: explicit weights, no early stop, checkpoints.
+struct WeightedCall {
+    const float *alpha, *beta;
+    float *ckpt;
+    int ckpt_every, n_ck;
+};
+
 mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint64_t *const syn[2],
                    const float *const prior[2], int pps, uint64_t *const cand[2], uint16_t *const kstat[2],
-                   float *const llr[2], bool persistent, hipStream_t s) {
+                   float *const llr[2], bool persistent, hipStream_t s, const WeightedCall *wc = nullptr) {
+    const int rule = wc ? (int)MBBP_WEIGHTED : c->params.rule;
+    if (rule == MBBP_WEIGHTED && !wc && (!c->walpha || !c->wbeta))
+        return fail(MBBP_EINVAL, "weighted rule: no weights set (mbbp_set_weights)");
     mbbp::BPArgs a{};
     a.part[0] = c->dp[0];
     a.part[1] = c->dp[1];
@@ -551,7 +571,14 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     a.T = c->T;
     a.alpha = c->params.alpha;
     a.rmax = c->params.r_max;
-    a.fixed_T = (c->params.flags & MBBP_FLAG_FIXED_T) ? 1 : 0;
+    a.fixed_T = (wc || (c->params.flags & MBBP_FLAG_FIXED_T)) ? 1 : 0;
+    if (rule == MBBP_WEIGHTED) {
+        a.walpha = wc ? wc->alpha : c->walpha;
+        a.wbeta = wc ? wc->beta : c->wbeta;
+        a.ckpt = wc ? wc->ckpt : nullptr;
+        a.ckpt_every = wc ? wc->ckpt_every : 1;
+        a.n_ck = wc ? wc->n_ck : 0;
+    }
     a.shots = shots;
     a.prior_per_shot = pps;
     for (int p = 0; p < 2; ++p) {
@@ -571,7 +598,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     a.item_order = persistent ? c->item_order + (part0 == 1 ? 0 : 0) : nullptr;
     if (persistent && nparts != 2) a.item_order = nullptr;
     a.queue = c->w_queue;
-    if (!inst_layout(c, part0, nparts, pps != 0, c->schedule, a))
+    if (!inst_layout(c, part0, nparts, pps != 0, c->schedule, rule, a))
         return fail(MBBP_EUNSUPPORTED, "code too large for the BP kernel's register tables");
     mbbp::BPConfig run = cfg;
     if (persistent) {
@@ -589,7 +616,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         MBBP_HIP(hipEventCreate(&ev1));
         MBBP_HIP(hipEventRecord(ev0, s));
     }
-    hipError_t e = mbbp::launch_bp(a, run, c->schedule, c->params.rule, s);
+    hipError_t e = mbbp::launch_bp(a, run, c->schedule, rule, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("bp launch: ") + hipGetErrorString(e));
     if (c->timing) {
         MBBP_HIP(hipEventRecord(ev1, s));
@@ -729,7 +756,10 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
     mbbp_params prm;
     mbbp_params_default(&prm);
     if (params) prm = *params;
-    if (prm.rule != MBBP_NMS && prm.rule != MBBP_SPA) return fail(MBBP_EINVAL, "unknown rule");
+    if (prm.rule != MBBP_NMS && prm.rule != MBBP_SPA && prm.rule != MBBP_WEIGHTED)
+        return fail(MBBP_EINVAL, "unknown rule");
+    if (prm.rule == MBBP_WEIGHTED && schedule != MBBP_FLOODING)
+        return fail(MBBP_EUNSUPPORTED, "the weighted rule is built for the flooding schedule");
     if (prm.select != MBBP_MIN_WEIGHT && prm.select != MBBP_FWS) return fail(MBBP_EINVAL, "unknown select rule");
     if (!(prm.alpha > 0.0f) || !(prm.r_max > 0.0f) || !std::isfinite(prm.alpha) || !std::isfinite(prm.r_max))
         return fail(MBBP_EINVAL, "alpha and r_max must be positive and finite");
@@ -1211,6 +1241,130 @@ mbbp_status mbbp_edge_counts(mbbp_ctx *ctx, int32_t part, int64_t *edges) {
     if (!ctx || !edges) return fail(MBBP_EINVAL, "null argument");
     if (part != 0 && part != 1) return fail(MBBP_EINVAL, "part must be 0 or 1");
     for (int l = 0; l < ctx->hp[part].L; ++l) edges[l] = ctx->hp[part].E[l];
+    return MBBP_OK;
+}
+
+static void drop_graphs(mbbp_ctx *ctx) {
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    ctx->graphs.clear();
+}
+
+mbbp_status mbbp_set_weights(mbbp_ctx *ctx, const float *alpha, const float *beta) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if ((alpha == nullptr) != (beta == nullptr)) return fail(MBBP_EINVAL, "alpha and beta: both or neither");
+    if (ctx->walpha != alpha || ctx->wbeta != beta) drop_graphs(ctx);  // captured launches hold the pointers
+    ctx->walpha = alpha;
+    ctx->wbeta = beta;
+    return MBBP_OK;
+}
+
+static mbbp_status wbp_common(mbbp_ctx *ctx, int32_t part, int64_t shots, const void *syn, const void *prior,
+                              const float *alpha, const float *beta, int32_t ckpt_every, int &n_ck, int &mpad) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (part != 0 && part != 1) return fail(MBBP_EINVAL, "part must be 0 (X) or 1 (Z)");
+    if (shots < 1 || shots > ctx->params.max_batch) return fail(MBBP_EINVAL, "shots out of range");
+    if (!syn || !prior || !alpha || !beta) return fail(MBBP_EINVAL, "null device pointer");
+    if (ckpt_every < 1) return fail(MBBP_EINVAL, "ckpt_every < 1");
+    if (ctx->schedule != MBBP_FLOODING) return fail(MBBP_EUNSUPPORTED, "the weighted rule is built for flooding");
+    const int T = ctx->T;
+    n_ck = T >= 1 ? (T + ckpt_every - 1) / ckpt_every - 1 : 0;
+    mbbp::BPArgs a{};
+    a.part[0] = ctx->dp[0];
+    a.part[1] = ctx->dp[1];
+    a.part0 = part;
+    a.nparts = 1;
+    if (!mbbp::bp_layout(a, mpad)) return fail(MBBP_EUNSUPPORTED, "code too large for the BP kernel");
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_wbp_ckpt_floats(mbbp_ctx *ctx, int32_t part, int64_t shots, int32_t ckpt_every, int64_t *floats) {
+    if (!floats) return fail(MBBP_EINVAL, "null floats");
+    int n_ck = 0, mpad = 0;
+    const float one = 0.0f;
+    mbbp_status st = wbp_common(ctx, part, shots, &one, &one, &one, &one, ckpt_every, n_ck, mpad);
+    if (st != MBBP_OK) return st;
+    *floats = shots * (int64_t)ctx->dp[part].L * n_ck * 8 * mpad;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_wbp_forward(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn, const float *prior,
+                             int32_t prior_per_shot, const float *alpha, const float *beta, int32_t ckpt_every,
+                             float *ckpt, float *llr, void *hip_stream) {
+    int n_ck = 0, mpad = 0;
+    mbbp_status st = wbp_common(ctx, part, shots, syn, prior, alpha, beta, ckpt_every, n_ck, mpad);
+    if (st != MBBP_OK) return st;
+    if (!llr) return fail(MBBP_EINVAL, "null llr");
+    if (n_ck > 0 && !ckpt) return fail(MBBP_EINVAL, "null ckpt (checkpoints are needed for this T and interval)");
+    WeightedCall wc{alpha, beta, ckpt, ckpt_every, n_ck};
+    const uint64_t *sy[2] = {syn, syn};
+    const float *pr[2] = {prior, prior};
+    float *ll[2] = {llr, llr};
+    return run_bp(ctx, part, 1, shots, sy, pr, prior_per_shot ? 1 : 0, ctx->cand, ctx->kstat, ll, false,
+                  static_cast<hipStream_t>(hip_stream), &wc);
+}
+
+mbbp_status mbbp_wbp_backward(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn, const float *prior,
+                              int32_t prior_per_shot, const float *alpha, const float *beta, int32_t ckpt_every,
+                              const float *ckpt, const float *grad_llr, float *grad_alpha, float *grad_beta,
+                              void *hip_stream) {
+    int n_ck = 0, mpad = 0;
+    mbbp_status st = wbp_common(ctx, part, shots, syn, prior, alpha, beta, ckpt_every, n_ck, mpad);
+    if (st != MBBP_OK) return st;
+    if (!grad_llr || !grad_alpha || !grad_beta) return fail(MBBP_EINVAL, "null gradient pointer");
+    if (n_ck > 0 && !ckpt) return fail(MBBP_EINVAL, "null ckpt");
+    const int T = ctx->T, L = ctx->dp[part].L;
+    if (T == 0) return MBBP_OK;
+    mbbp::BPArgs ba{};
+    ba.part[0] = ctx->dp[0];
+    ba.part[1] = ctx->dp[1];
+    ba.part0 = part;
+    ba.nparts = 1;
+    int pv = 0, pc = 0;
+    if (!mbbp::bp_passes(ba, pv, pc) || !mbbp::wbp_backward_supported(pv, pc))
+        return fail(MBBP_EUNSUPPORTED, "weighted adjoint: code too large (built for n <= 320, <= 320 checks)");
+    const mbbp::DevPart &D = ctx->dp[part];
+    mbbp::WBPBackArgs a{};
+    a.dpart = ctx->dparts + part;
+    a.L = L;
+    a.T = T;
+    a.shots = shots;
+    a.n_items = shots * L;
+    a.rmax = ctx->params.r_max;
+    a.syn = syn;
+    a.prior = prior;
+    a.prior_per_shot = prior_per_shot ? 1 : 0;
+    a.walpha = alpha;
+    a.wbeta = beta;
+    a.ckpt = ckpt;
+    a.ckpt_every = ckpt_every;
+    a.n_ck = n_ck;
+    a.grad_llr = grad_llr;
+    a.ws = D.Ws;
+    a.n = D.n;
+    const int bytes = (3 + ckpt_every) * 32 * mpad + D.Ws * 8 + (prior_per_shot ? D.n * 4 : 0);
+    a.inst_bytes = (bytes + 15) & ~15;
+    int wpb = 4;
+    while (wpb > 1 && (size_t)wpb * a.inst_bytes > mbbp::bp_lds_limit()) wpb /= 2;
+    if ((size_t)a.inst_bytes > mbbp::bp_lds_limit())
+        return fail(MBBP_EUNSUPPORTED, "weighted adjoint: checkpoint interval too long for LDS");
+    const size_t need = (size_t)a.n_items * T * sizeof(float2);
+    if (need > ctx->gpart_bytes) {
+        auto b = std::make_unique<DevBuf>();
+        hipError_t e = hipMalloc(&b->p, need);
+        if (e != hipSuccess) return fail(MBBP_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        ctx->gpart = std::move(b);
+        ctx->gpart_bytes = need;
+    }
+    a.partial = static_cast<float2 *>(ctx->gpart->p);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = mbbp::launch_wbp_backward(a, pv, pc, D.uniform_dc == 6 ? 6 : 8, wpb, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("adjoint launch: ") + hipGetErrorString(e));
+    e = mbbp::launch_wbp_reduce(a.partial, shots, T, L, grad_alpha, grad_beta, s);
+    if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("reduce launch: ") + hipGetErrorString(e));
     return MBBP_OK;
 }
 

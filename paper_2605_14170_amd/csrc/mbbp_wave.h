@@ -38,6 +38,12 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
     return v;
 }
 
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
 __device__ __forceinline__ float bitsf(uint32_t x) { return __uint_as_float(x); }
 

@@ -1,0 +1,328 @@
+"""GPU parity of the weighted (differentiable) decoder through the C ABI.
+
+* training forward (fixed T, every representation's P^(T)): bit-exact against the
+  single-precision oracle on random per-iteration, per-representation weights;
+* alpha = alpha_0, beta = 0: decoding with the weighted rule is bit-identical to
+  plain normalized min-sum (per-representation outputs and mbbp_run counters);
+* weighted decoding with early stop: bit-exact against the oracle;
+* adjoint: against autograd of the plain-PyTorch CPU reference (float32, whose
+  forward equals the kernel's bit for bit) and against FP64 central finite
+  differences of the oracle, away from non-smooth points;
+* checkpoint interval: gradients bit-identical for every interval;
+* a short Adam run lowers the training loss.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import codes
+from workloads.configs import WORKLOADS
+
+from . import wbp_reference as ref
+from .common import bases_for, f32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_14170_amd as m
+    return m
+
+
+def words(t):
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def make(pk, code, wl, T, rule=0, max_batch=4096, mode=None, L=None):
+    if mode is None:
+        bx = bases_for(code.hx, wl, oracle.build_bases)
+        bz = bases_for(code.hz, wl, oracle.build_bases)
+    else:
+        from workloads.perms import check_permutations
+        bx = oracle.build_bases(code.hx, mode, L, check_permutations(code.hx.shape[0], L, 1))
+        bz = oracle.build_bases(code.hz, mode, L, check_permutations(code.hz.shape[0], L, 1))
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, T, alpha=wl.alpha, rule=rule, max_batch=max_batch)
+    return dec, bx, bz
+
+
+def rand_weights(T, L, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.55, 1.15, size=(T, L)).astype(np.float32)
+    b = rng.uniform(0.0, 0.45, size=(T, L)).astype(np.float32)
+    return a, b
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda")
+
+
+# ------------------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("key,T,p,shots,pps", [("bb72_L4_T20", 12, 0.06, 600, False),
+                                               ("bb144_L16_T50", 25, 0.05, 200, False),
+                                               ("bb72_L4_T20", 9, 0.08, 300, True)])
+def test_weighted_forward_bit_exact(pk, key, T, p, shots, pps):
+    wl = WORKLOADS[key]
+    code = wl.code()
+    dec, bx, bz = make(pk, code, wl, T, max_batch=shots)
+    a, b = rand_weights(T, wl.L, 3)
+    say(f"weighted forward {key} T={T} p={p} shots={shots} per-shot priors={pps}")
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 100, shots)
+    if pps:
+        mu = np.random.default_rng(9).uniform(1.0, 4.0, size=(shots, code.n)).astype(np.float32)
+    else:
+        mu = np.full(code.n, f32(oracle.prior_llr(p)), np.float32)
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        llr, _ = dec.wbp_forward(part, syn, dev(mu), dev(a), dev(b), ckpt_every=5)
+        torch.cuda.synchronize()
+        r = oracle.decode(h, bp, rows, words(syn), mu.astype(np.float64), T, rule=oracle.WNMS, fixed_T=True,
+                          want_llr=True, precision="f32", walpha=a, wbeta=b)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), r.llr.astype(np.float32).view(np.uint32),
+                                      err_msg=f"part {part}")
+    dec.close()
+
+
+@pytest.mark.parametrize("factory", [codes.surface13, codes.toric18])
+def test_weighted_forward_small_codes_bit_exact(pk, factory):
+    """Rows of weight 2..4 (padded row slots) and low-degree variables."""
+    code = factory()
+    L, T, shots, p = 3, 10, 500, 0.1
+    wl = WORKLOADS["bb72_L4_T20"]
+    dec, bx, bz = make(pk, code, wl, T, max_batch=shots, mode="ramp", L=L)
+    a, b = rand_weights(T, L, 4)
+    ex, ez, sx, sz = dec.sample(5, p, 0, shots)
+    mu = np.full(code.n, f32(oracle.prior_llr(p)), np.float32)
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        llr, _ = dec.wbp_forward(part, syn, dev(mu), dev(a), dev(b), ckpt_every=3)
+        torch.cuda.synchronize()
+        r = oracle.decode(h, bp, rows, words(syn), mu.astype(np.float64), T, rule=oracle.WNMS, fixed_T=True,
+                          want_llr=True, precision="f32", walpha=a, wbeta=b)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), r.llr.astype(np.float32).view(np.uint32))
+    dec.close()
+
+
+def test_weighted_plain_weights_equal_nms(pk):
+    """alpha = alpha_0 and beta = 0 everywhere: the weighted rule decodes exactly as
+    normalized min-sum (per-representation outputs and whole-path counters)."""
+    wl = WORKLOADS["bb144_L16_T50"]
+    code = wl.code()
+    shots, p, T = 3000, 0.07, wl.T
+    plain, bx, bz = make(pk, code, wl, T, max_batch=shots)
+    wdec, _, _ = make(pk, code, wl, T, rule=pk.WEIGHTED, max_batch=shots)
+    a = torch.full((T, wl.L), wl.alpha, dtype=torch.float32, device="cuda")
+    b = torch.zeros((T, wl.L), dtype=torch.float32, device="cuda")
+    wdec.set_weights(a, b)
+    say(f"weighted == plain at alpha0, beta 0: bb144 p={p} shots={shots}")
+    ex, ez, sx, sz = plain.sample(wl.seed, p, 0, shots)
+    prior = torch.full((code.n,), f32(oracle.prior_llr(p)), dtype=torch.float32, device="cuda")
+    for part, syn in ((0, sx), (1, sz)):
+        c0, k0, l0 = plain.decode_detail(part, syn, prior, want_llr=True)
+        c1, k1, l1 = wdec.decode_detail(part, syn, prior, want_llr=True)
+        torch.cuda.synchronize()
+        assert torch.equal(c0, c1) and torch.equal(k0, k1)
+        assert np.array_equal(l0.cpu().numpy().view(np.uint32), l1.cpu().numpy().view(np.uint32))
+    n0 = plain.run(wl.seed, p, 777, shots)
+    n1 = wdec.run(wl.seed, p, 777, shots)
+    torch.cuda.synchronize()
+    assert torch.equal(n0, n1), (n0.tolist(), n1.tolist())
+    say(f"  counters {n0.tolist()}")
+    plain.close()
+    wdec.close()
+
+
+def test_weighted_decode_early_stop_bit_exact(pk):
+    """Decoding with learned-style weights (early stop, list decision) against the
+    single-precision oracle."""
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    T, shots, p = 20, 2000, 0.07
+    dec, bx, bz = make(pk, code, wl, T, rule=pk.WEIGHTED, max_batch=shots)
+    a, b = rand_weights(T, wl.L, 5)
+    A, B = dev(a), dev(b)
+    dec.set_weights(A, B)
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 0, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    out = dec.decode(sx, sz, prior, prior)
+    for part, h, (bp, rows), syn, corr in ((0, code.hz, bz, sx, out["corr_x"]), (1, code.hx, bx, sz, out["corr_z"])):
+        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+        torch.cuda.synchronize()
+        r = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), T, rule=oracle.WNMS, want_llr=True,
+                          precision="f32", walpha=a, wbeta=b)
+        ks = kstat.cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(words(cand), r.cand)
+        np.testing.assert_array_equal(ks & 0x7FFF, r.K)
+        np.testing.assert_array_equal((ks >> 15).astype(bool), r.conv)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), r.llr.astype(np.float32).view(np.uint32))
+        np.testing.assert_array_equal(words(corr), r.corr)
+    dec.close()
+
+
+# ------------------------------------------------------------------------ adjoint
+
+def _gpu_grads(pk, dec, sx, sz, prior, a, b, ex, ez, every, weight=None):
+    from paper_2605_14170_amd import weighted
+    A = dev(a).requires_grad_(True)
+    B = dev(b).requires_grad_(True)
+    P = weighted.WeightedBP.apply(A, B, dec, sx, sz, prior, prior, every)
+    if weight is None:
+        loss = weighted.loss_fn(P, ex, ez, dec.n)
+    else:
+        y = torch.stack([weighted.unpack_bits(ex, dec.n), weighted.unpack_bits(ez, dec.n)])[:, :, None, :]
+        x = torch.nn.functional.binary_cross_entropy_with_logits(-P, y.expand_as(P), reduction="none")
+        loss = (x * weight).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return P.detach(), float(loss.detach()), A.grad.cpu().numpy(), B.grad.cpu().numpy()
+
+
+def _ref_grads(code, bx, bz, sx, sz, mu, a, b, ex, ez, T, L, dtype):
+    A = torch.tensor(a, dtype=dtype, requires_grad=True)
+    B = torch.tensor(b, dtype=dtype, requires_grad=True)
+    Ps = []
+    for h, (bp, rows), syn, err in ((code.hz, bz, sx, ex), (code.hx, bx, sz, ez)):
+        s = oracle.unpack(words(syn), h.shape[0])
+        per = []
+        for l in range(L):
+            rep = ref.Rep(h, rows[bp[l]:bp[l + 1]])
+            per.append(ref.forward(rep, s, torch.tensor(mu, dtype=dtype), A[:, l], B[:, l], T))
+        Ps.append(torch.stack(per, 1))
+    P = torch.stack(Ps)
+    y = torch.stack([torch.tensor(oracle.unpack(words(ex), code.n), dtype=dtype),
+                     torch.tensor(oracle.unpack(words(ez), code.n), dtype=dtype)])[:, :, None, :]
+    loss = torch.nn.functional.binary_cross_entropy_with_logits(-P, y.expand_as(P))
+    loss.backward()
+    return P.detach(), float(loss.detach()), A.grad.numpy(), B.grad.numpy()
+
+
+@pytest.mark.parametrize("key,T,p,shots,pps", [("bb72_L4_T20", 10, 0.07, 64, False),
+                                               ("bb72_L4_T20", 10, 0.07, 64, True),
+                                               ("bb144_L16_T50", 25, 0.05, 24, False)])
+def test_adjoint_matches_torch_reference(pk, key, T, p, shots, pps):
+    wl = WORKLOADS[key]
+    code = wl.code()
+    dec, bx, bz = make(pk, code, wl, T, max_batch=shots)
+    a, b = rand_weights(T, wl.L, 7)
+    say(f"adjoint vs torch reference {key} T={T} shots={shots} per-shot priors={pps}")
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 0, shots)
+    if pps:
+        mu = np.random.default_rng(2).uniform(1.0, 4.0, size=(shots, code.n)).astype(np.float32)
+    else:
+        mu = np.full(code.n, f32(oracle.prior_llr(p)), np.float32)
+    Pg, lg, ga, gb = _gpu_grads(pk, dec, sx, sz, dev(mu), a, b, ex, ez, 5)
+    Pr, lr, ra, rb = _ref_grads(code, bx, bz, sx, sz, mu, a, b, ex, ez, T, wl.L, torch.float32)
+    assert np.array_equal(Pg.cpu().numpy().view(np.uint32), Pr.numpy().view(np.uint32)), "forward differs"
+    for name, g, r in (("alpha", ga, ra), ("beta", gb, rb)):
+        scale = np.abs(r).max()
+        err = np.abs(g - r).max()
+        say(f"  d/d{name}: max |grad| {scale:.3e}, max abs diff {err:.3e}")
+        np.testing.assert_allclose(g, r, rtol=2e-3, atol=2e-4 * scale, err_msg=name)
+    dec.close()
+
+
+def test_adjoint_matches_fd_of_fp64_oracle(pk):
+    """GPU gradients against central differences (h = 1e-6) of the FP64 oracle's
+    loss, restricted (by loss weights) to instances whose FP64 trajectory stays
+    1e-3 away from every non-smooth point; random per-qubit priors."""
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    T, shots, p, L = 8, 16, 0.08, wl.L
+    dec, bx, bz = make(pk, code, wl, T, max_batch=shots)
+    a, b = rand_weights(T, L, 8)
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 4000, shots)
+    mu = np.random.default_rng(13).uniform(1.0, 4.0, size=(shots, code.n)).astype(np.float32)
+    mu64 = mu.astype(np.float64)
+    tgt = [oracle.unpack(words(ex), code.n).astype(np.float64), oracle.unpack(words(ez), code.n).astype(np.float64)]
+
+    def oracle_P(wa, wb):
+        out, margins = [], []
+        for h, (bp, rows), syn in ((code.hz, bz, sx), (code.hx, bx, sz)):
+            r = oracle.decode(h, bp, rows, words(syn), mu64, T, rule=oracle.WNMS, fixed_T=True, want_llr=True,
+                              walpha=wa, wbeta=wb)
+            out.append(r.llr)
+            margins.append(r.margin[..., 0])
+        return np.stack(out), np.stack(margins)
+
+    a64, b64 = a.astype(np.float64), b.astype(np.float64)
+    _, margin = oracle_P(a64, b64)
+    mask = (margin > 1e-3).astype(np.float64)  # [2, shots, L]
+    assert mask.mean() > 0.5
+    wts = mask / (mask.sum() * code.n)
+
+    def loss64(wa, wb):
+        P, _ = oracle_P(wa, wb)
+        x = -P
+        tot = 0.0
+        for part in range(2):
+            y = tgt[part][:, None, :]
+            bce = np.maximum(x[part], 0) - x[part] * y + np.log1p(np.exp(-np.abs(x[part])))
+            tot += float((bce * wts[part][:, :, None]).sum())
+        return tot
+
+    weight = torch.tensor(wts, dtype=torch.float32, device="cuda")[..., None]
+    _, _, ga, gb = _gpu_grads(pk, dec, sx, sz, dev(mu), a, b, ex, ez, 5, weight=weight)
+    h = 1e-6
+    for name, g in (("alpha", ga), ("beta", gb)):
+        fd = np.zeros_like(g, dtype=np.float64)
+        for t in range(T):
+            for l in range(L):
+                wa, wb = a64.copy(), b64.copy()
+                tgtw = wa if name == "alpha" else wb
+                tgtw[t, l] += h
+                lp = loss64(wa, wb)
+                tgtw[t, l] -= 2 * h
+                lm = loss64(wa, wb)
+                fd[t, l] = (lp - lm) / (2 * h)
+        scale = np.abs(fd).max()
+        err = np.abs(g - fd).max()
+        say(f"  FD d/d{name}: max |grad| {scale:.3e}, max abs diff {err:.3e}")
+        np.testing.assert_allclose(g, fd, rtol=1e-2, atol=1e-3 * scale, err_msg=name)
+    dec.close()
+
+
+def test_checkpoint_interval_bit_identical(pk):
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    T, shots, p = 12, 256, 0.07
+    dec, bx, bz = make(pk, code, wl, T, max_batch=shots)
+    a, b = rand_weights(T, wl.L, 10)
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 0, shots)
+    prior = torch.full((code.n,), f32(oracle.prior_llr(p)), dtype=torch.float32, device="cuda")
+    res = {}
+    for every in (1, 2, 5, 7, 12):
+        P, _, ga, gb = _gpu_grads(pk, dec, sx, sz, prior, a, b, ex, ez, every)
+        res[every] = (P.cpu().numpy(), ga, gb)
+    base = res[1]
+    for every, (P, ga, gb) in res.items():
+        assert np.array_equal(P.view(np.uint32), base[0].view(np.uint32)), every
+        assert np.array_equal(ga.view(np.uint32), base[1].view(np.uint32)), every
+        assert np.array_equal(gb.view(np.uint32), base[2].view(np.uint32)), every
+    say(f"  gradients identical for intervals {sorted(res)}")
+    dec.close()
+
+
+def test_short_training_lowers_loss(pk):
+    from paper_2605_14170_amd import weighted
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    T, batch, steps, p = 8, 512, 40, 0.07
+    dec, bx, bz = make(pk, code, wl, T, max_batch=batch)
+    alpha, beta, losses = weighted.train(dec, seed=3, p=p, batch=batch, steps=steps, lr=2e-2)
+    first, last = np.mean(losses[:5]), np.mean(losses[-5:])
+    say(f"  training loss {first:.5f} -> {last:.5f}")
+    assert last < first
+    assert torch.isfinite(alpha).all() and torch.isfinite(beta).all()
+    dec.close()
