@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -51,6 +53,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-shots", type=int, default=60000, help="oracle sample: shots per error rate")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--train-steps", type=int, default=2000, help="weighted workload: Adam steps")
+    ap.add_argument("--train-batch", type=int, default=4096, help="weighted workload: shots per Adam step")
+    ap.add_argument("--lr", type=float, default=1e-3, help="weighted workload: Adam learning rate")
+    ap.add_argument("--val-every", type=int, default=100, help="weighted workload: validate every k steps (0: off)")
+    ap.add_argument("--val-shots", type=int, default=200_000, help="weighted workload: validation shots")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -79,12 +86,13 @@ def recorded_traffic(workload, shots_per_launch):
         return None
 
 
-def build_decoder(pk, wl, code, max_batch):
+def build_decoder(pk, wl, code, max_batch, T=None, rule=0):
     from workloads.perms import check_permutations
     perms = lambda h: check_permutations(h.shape[0], max(wl.L, 8), wl.perm_seed)  # noqa: E731
     bx = pk.build_bases(code.hx, wl.basis_mode, wl.L, perms(code.hx))
     bz = pk.build_bases(code.hz, wl.basis_mode, wl.L, perms(code.hz))
-    dec = pk.Decoder(code.hx, code.hz, bx, bz, wl.T, alpha=wl.alpha, max_batch=max_batch)
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, wl.T if T is None else T, alpha=wl.alpha, rule=rule,
+                     max_batch=max_batch)
     return dec, bx, bz
 
 
@@ -108,6 +116,128 @@ def cpu_baseline(wl, code, bx, bz, shots_per_p, threads):
                 edge_updates_per_s=edges / dt, seconds=dt,
                 sample=f"{shots_per_p} shots at each p in {list(wl.ps)} ({shots} shots), FP64 oracle, "
                        f"{threads} threads over disjoint shot ranges")
+
+
+def wilson(k, n, z=1.959963984540054):
+    """Wilson 95% interval of a binomial proportion."""
+    import math
+    if n == 0:
+        return (0.0, 1.0)
+    ph = k / n
+    den = 1 + z * z / n
+    c = (ph + z * z / (2 * n)) / den
+    h = z * math.sqrt(ph * (1 - ph) / n + z * z / (4 * n * n)) / den
+    return (max(0.0, c - h), min(1.0, c + h))
+
+
+def weighted_main(args, wl, code):
+    """Weighted decoder: train (alpha, beta) with Adam on fresh shots, then decode
+    the same fresh evaluation shots with the learned weights (T = wl.T) and with
+    plain normalized min-sum at T = wl.T and T = 50.  One timed step = one
+    evaluation pass of the weighted decoder over `shots` shots."""
+    import torch
+    import paper_2605_14170_amd as pk
+    from paper_2605_14170_amd import weighted
+
+    p = wl.ps[0]
+    shots = args.shots or wl.shots
+    batch, steps = args.train_batch, args.train_steps
+    torch.cuda.set_device(0)
+    trainer, bx, bz = build_decoder(pk, wl, code, batch)
+    print(f"# {wl.key}: training {steps} Adam steps, batch {batch}, lr {args.lr}, p {p}", file=sys.stderr,
+          flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+
+    def cb(k, v):
+        if k % 200 == 0 or k == steps - 1:
+            print(f"# step {k} loss {v:.6f}", file=sys.stderr, flush=True)
+
+    # held-out validation shots (a range disjoint from training and evaluation)
+    vdec, _, _ = build_decoder(pk, wl, code, args.val_shots, rule=pk.WEIGHTED)
+    va = torch.empty((wl.T, wl.L), dtype=torch.float32, device="cuda")
+    vb = torch.empty_like(va)
+    vdec.set_weights(va, vb)
+
+    def validate(a, b):
+        va.copy_(a)
+        vb.copy_(b)
+        cnt = vdec.run(wl.seed, p, 5 * 10**8, args.val_shots)
+        return float(cnt[pk.CNT_FAIL].item()) / args.val_shots
+
+    tr = weighted.train(trainer, seed=wl.seed + 1000, p=p, batch=batch, steps=steps, lr=args.lr,
+                        alpha0=wl.alpha, ckpt_every=5, callback=cb,
+                        validate=validate if args.val_every > 0 else None, val_every=args.val_every)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    trainer.close()
+    vdec.close()
+    alpha, beta, losses = tr.alpha, tr.beta, tr.losses
+    eval_shot0 = 10**9
+    res = {}
+    if args.val_every > 0:
+        bdec, _, _ = build_decoder(pk, wl, code, shots, rule=pk.WEIGHTED)
+        bdec.set_weights(tr.best_alpha.contiguous(), tr.best_beta.contiguous())
+        cnt = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
+        for k in range(args.steps):
+            bdec.run(wl.seed, p, eval_shot0 + k * shots, shots, cnt)
+        res[f"weighted_T{wl.T}_best_validation"] = dict(fails=int(cnt[pk.CNT_FAIL].item()), shots=shots * args.steps,
+                                                        step=tr.best_step)
+        bdec.close()
+    wdec, _, _ = build_decoder(pk, wl, code, shots, rule=pk.WEIGHTED)
+    wdec.set_weights(alpha.contiguous(), beta.contiguous())
+    for k in range(args.warmup):
+        wdec.run(wl.seed, p, 10**12 + k * shots, shots)
+    torch.cuda.synchronize()
+    counters = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
+    wdec.bp_time(reset=True)
+    wdec.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        wdec.run(wl.seed, p, eval_shot0 + k * shots, shots, counters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    wdec.set_timing(False)
+    bp_ms, bp_launches = wdec.bp_time(reset=True)
+    c = counters.cpu().numpy()
+    total = shots * args.steps
+    res[f"weighted_T{wl.T}_final"] = dict(fails=int(c[pk.CNT_FAIL]), shots=total)
+    wdec.close()
+    for T in (wl.T, 50):
+        dec, _, _ = build_decoder(pk, wl, code, shots, T=T)
+        cnt = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
+        for k in range(args.steps):
+            dec.run(wl.seed, p, eval_shot0 + k * shots, shots, cnt)
+        torch.cuda.synchronize()
+        cc = cnt.cpu().numpy()
+        res[f"plain_T{T}"] = dict(fails=int(cc[pk.CNT_FAIL]), shots=total)
+        dec.close()
+    for v in res.values():
+        v["ler"] = v["fails"] / v["shots"]
+        v["ci95"] = wilson(v["fails"], v["shots"])
+    edges = int(c[pk.CNT_EDGE_UPDATES])
+    bp_avg_s = bp_ms / 1e3 / max(1, bp_launches)
+    achieved = edges / max(1, bp_launches) * OPS_PER_EDGE_UPDATE / bp_avg_s / 1e12 if bp_launches else None
+    line = dict(metric="MBBP-LD decoded shots/s and BP edge-msg updates/s at matched logical error rate",
+                value=total / dt, unit="shots/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=dt * 1e3 / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32", data="synthetic",
+                config=dict(workload=wl.key, code=code.name, n=code.n, L=wl.L, T=wl.T, p=p, shots_per_step=shots,
+                            rule="weighted min-sum (learned alpha, beta per iteration and representation)",
+                            schedule="flooding", eval_shot0=eval_shot0),
+                edge_updates_per_s=edges / dt,
+                training=dict(steps=steps, batch=batch, lr=args.lr, seconds=train_s,
+                              ms_per_adam_step=train_s * 1e3 / max(1, steps), first_loss=losses[0],
+                              last_loss=float(np.mean(losses[-20:])), ckpt_every=5,
+                              alpha_range=[float(alpha.min()), float(alpha.max())],
+                              beta_range=[float(beta.min()), float(beta.max())],
+                              validation=[(k, v) for k, v in tr.validation]),
+                ler=res,
+                roofline=dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="T lane-op/s",
+                              frac=(achieved / VALU_PEAK_TOPS) if achieved else None, traffic=None,
+                              kernel="bp_kernel (weighted)", avg_launch_ms=bp_avg_s * 1e3))
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -135,6 +265,8 @@ def main():
 
     wl = WORKLOADS[args.workload]
     code = wl.code()
+    if "weighted" in wl.key:
+        return weighted_main(args, wl, code)
     shots = args.shots or wl.shots
     torch.cuda.set_device(0)
     dec, bx, bz = build_decoder(pk, wl, code, shots)

@@ -11,6 +11,7 @@ averaged over shots, representations, qubits and both parts.
 
 from __future__ import annotations
 
+import dataclasses
 from typing import Callable, Optional
 
 from . import Decoder, prior_llr
@@ -75,18 +76,43 @@ def loss_fn(P, err_x, err_z, n: int):
     return torch.nn.functional.binary_cross_entropy_with_logits(-P, y.expand_as(P))
 
 
+@dataclasses.dataclass
+class TrainResult:
+    alpha: object            # [T, L] after the last step
+    beta: object
+    losses: list             # training loss of every step
+    best_alpha: object       # weights of the best validation score (the last ones without validation)
+    best_beta: object
+    best_step: int           # step after which they were taken (-1: initial weights)
+    validation: list         # (step, score) of every validation
+
+
 def train(dec: Decoder, seed: int, p: float, batch: int, steps: int, lr: float = 1e-3,
           alpha0: float = 0.875, ckpt_every: int = 5, shot0: int = 0,
-          callback: Optional[Callable[[int, float], None]] = None):
+          callback: Optional[Callable[[int, float], None]] = None,
+          validate: Optional[Callable[[object, object], float]] = None, val_every: int = 0) -> TrainResult:
     """Adam on (alpha, beta) from alpha = alpha0, beta = 0.  Step k trains on the fresh
     shots [shot0 + k * batch, shot0 + (k + 1) * batch) of the counter-based sampler
-    at error rate p.  Returns (alpha, beta, losses)."""
+    at error rate p.  With `validate` (weights -> score, lower is better) the
+    initial weights and those after every val_every steps are scored and the best
+    are kept as well."""
     torch = _torch()
     alpha = torch.full((dec.T, dec.L), float(alpha0), dtype=torch.float32, device="cuda", requires_grad=True)
     beta = torch.zeros((dec.T, dec.L), dtype=torch.float32, device="cuda", requires_grad=True)
     opt = torch.optim.Adam([alpha, beta], lr=lr)
     prior = torch.full((dec.n,), prior_llr(p), dtype=torch.float32, device="cuda")
-    losses = []
+    losses, vals = [], []
+    best = (float("inf"), -1, alpha.detach().clone(), beta.detach().clone())
+
+    def check(k):
+        nonlocal best
+        v = float(validate(alpha.detach().clone(), beta.detach().clone()))
+        vals.append((k, v))
+        if v < best[0]:
+            best = (v, k, alpha.detach().clone(), beta.detach().clone())
+
+    if validate is not None and val_every > 0:
+        check(-1)
     for k in range(steps):
         ex, ez, sx, sz = dec.sample(seed, p, shot0 + k * batch, batch)
         P = WeightedBP.apply(alpha, beta, dec, sx, sz, prior, prior, ckpt_every)
@@ -98,4 +124,9 @@ def train(dec: Decoder, seed: int, p: float, batch: int, steps: int, lr: float =
         losses.append(v)
         if callback is not None:
             callback(k, v)
-    return alpha.detach().clone(), beta.detach().clone(), losses
+        if validate is not None and val_every > 0 and (k + 1) % val_every == 0:
+            check(k)
+    a, b = alpha.detach().clone(), beta.detach().clone()
+    if validate is None or val_every <= 0:
+        return TrainResult(a, b, losses, a, b, steps - 1, vals)
+    return TrainResult(a, b, losses, best[2], best[3], best[1], vals)

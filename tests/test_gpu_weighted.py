@@ -320,9 +320,17 @@ def test_short_training_lowers_loss(pk):
     code = wl.code()
     T, batch, steps, p = 8, 512, 40, 0.07
     dec, bx, bz = make(pk, code, wl, T, max_batch=batch)
-    alpha, beta, losses = weighted.train(dec, seed=3, p=p, batch=batch, steps=steps, lr=2e-2)
-    first, last = np.mean(losses[:5]), np.mean(losses[-5:])
+    calls = []
+
+    def validate(a, b):
+        calls.append(1)
+        return float(len(calls) % 3)  # any deterministic score: checks the bookkeeping
+
+    res = weighted.train(dec, seed=3, p=p, batch=batch, steps=steps, lr=2e-2, validate=validate, val_every=10)
+    first, last = np.mean(res.losses[:5]), np.mean(res.losses[-5:])
     say(f"  training loss {first:.5f} -> {last:.5f}")
     assert last < first
-    assert torch.isfinite(alpha).all() and torch.isfinite(beta).all()
+    assert torch.isfinite(res.alpha).all() and torch.isfinite(res.beta).all()
+    assert [k for k, _ in res.validation] == [-1, 9, 19, 29, 39]
+    assert res.best_step == 19  # scores 1, 2, 0, 1, 2
     dec.close()
