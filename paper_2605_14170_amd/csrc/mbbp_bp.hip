@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? (
 void bp_wave_kernel(BPArgs a) {
     using LY = Layout<PC, RULE>;
     static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
-    constexpr int Mpad = LY::Mpad;
+    constexpr int S = LY::S;  // slot stride of the LDS arrays (words)
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -97,9 +97,8 @@ void bp_wave_kernel(BPArgs a) {
     while (item < a.n_items) {
         const ItemPos ip = decode_item(a, item);
         const DevPart *pt = a.dparts + ip.part;
-        const int n = pt->n, m = pt->m, Mmax = pt->Mmax, W = pt->W, Ws = pt->Ws, L = pt->L;
+        const int n = pt->n, Mmax = pt->Mmax, W = pt->W, Ws = pt->Ws, L = pt->L;
         const int l = ip.l;
-        const int Ml = pt->M[l];
         const int vp = (n + 63) >> 6;
         const int key = ip.part * 256 + l;
         if (key != cur_key) {
@@ -127,7 +126,7 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
                 for (int k = 0; k < kMaxVarDegree; ++k) {
                     const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-                    ea[v][k] = ibase_addr + 4u * ((e & 7u) * (uint32_t)Mpad + (e >> 3));
+                    ea[v][k] = ibase_addr + 4u * ((e & 7u) * (uint32_t)S + (e >> 3));
                 }
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
@@ -140,7 +139,7 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
                 for (int c = 0; c < PC; ++c) {
                     const int j = c * 64 + lane;
-                    cwp[c] = j < Ml ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
+                    cwp[c] = j < Mmax ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
                 }
             }
         }
@@ -171,12 +170,13 @@ void bp_wave_kernel(BPArgs a) {
                     mu[v] = (v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
                 }
             }
-            uint32_t sbits = 0;
+            uint32_t sbits = 0, rowv = 0;  // syndrome bit and "real check" flag per pass
 #pragma unroll
             for (int c = 0; c < PC; ++c) {
                 const int j = c * 64 + lane;
-                if (j < Ml) {
-                    const int src = j < m ? j : csrc[j];
+                const int src = j < Mmax ? csrc[j] : kJunkRow;
+                if (src != kJunkRow) {
+                    rowv |= 1u << c;
                     uint32_t bit = 0;
                     if (src >= 0) {
                         bit = (uint32_t)(synl[src >> 6] >> (src & 63)) & 1u;
@@ -233,8 +233,8 @@ void bp_wave_kernel(BPArgs a) {
                         const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
                         uint32_t par = (sbits >> c) & 1u;
 #pragma unroll
-                        for (int k = 0; k < DC; ++k) par ^= drow[4 * k * Mpad];
-                        unsat |= par & (j < Ml ? 1u : 0u);
+                        for (int k = 0; k < DC; ++k) par ^= drow[4 * k * S];
+                        unsat |= par & ((rowv >> c) & 1u);
                     }
                     const bool sat = __ballot(unsat != 0u) == 0ull;
                     if (!a.fixed_T) {
@@ -266,7 +266,7 @@ void bp_wave_kernel(BPArgs a) {
                                         if (u < dmax_rep - 1) {
                                             const uint32_t eo = oth[u];
                                             const float x = *lds_ptr_f32(ibase_addr +
-                                                                         4u * ((eo & 7u) * (uint32_t)Mpad + (eo >> 3)));
+                                                                         4u * ((eo & 7u) * (uint32_t)S + (eo >> 3)));
                                             acc += u < deg - 1 ? x : 0.0f;
                                         }
                                     }
@@ -275,7 +275,7 @@ void bp_wave_kernel(BPArgs a) {
                                 CheckRule<RULE>::template apply<DC>(q, (int)sb, alpha, rmax);
                                 lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
 #pragma unroll
-                                for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
+                                for (int k = 0; k < DC; ++k) row[k * S] = q[k];
                             }
                             wave_sync();
                         }
@@ -289,8 +289,8 @@ void bp_wave_kernel(BPArgs a) {
                         if (a.ckpt && it > 0 && it < T && it % a.ckpt_every == 0) {
                             const uint4 *src = reinterpret_cast<const uint4 *>(ibase + LY::kROff);
                             uint4 *dst = reinterpret_cast<uint4 *>(
-                                a.ckpt + (((size_t)shot * L + l) * a.n_ck + (it / a.ckpt_every - 1)) * (8 * Mpad));
-                            for (int i = lane; i < 2 * Mpad; i += 64) dst[i] = src[i];
+                                a.ckpt + (((size_t)shot * L + l) * a.n_ck + (it / a.ckpt_every - 1)) * (8 * S));
+                            for (int i = lane; i < 2 * S; i += 64) dst[i] = src[i];
                         }
                     }
                     // ---------------- variable phase
@@ -300,15 +300,16 @@ void bp_wave_kernel(BPArgs a) {
                             const int deg = (int)(vinfo[v] >> 16);
                             float Pv = 0.0f;
                             bool d = false;
+                            const bool prevd = (decb >> v) & 1u;
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_rule<1, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 2: var_rule<2, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 3: var_rule<3, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 4: var_rule<4, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 5: var_rule<5, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 6: var_rule<6, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 7: var_rule<7, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 8: var_rule<8, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 1: var_rule<1, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 2: var_rule<2, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 3: var_rule<3, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 4: var_rule<4, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 5: var_rule<5, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 6: var_rule<6, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 7: var_rule<7, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 8: var_rule<8, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
@@ -322,6 +323,9 @@ void bp_wave_kernel(BPArgs a) {
                     // ---------------- check phase: syndrome test of the decisions, c->v messages.
                     // Rows beyond the representation's checks are junk rows (unused by it).
                     uint32_t unsat = 0;
+                    // every pass's loads are issued before any pass's stores (rows of different
+                    // passes are disjoint), so the LDS latency of later passes overlaps
+                    float qa[PC][DC];
                     float w_alpha = 0.0f, w_beta = 0.0f, w_keep = 1.0f;
                     if constexpr (RULE == kRuleWeighted) {
                         if (it < T) {
@@ -333,38 +337,43 @@ void bp_wave_kernel(BPArgs a) {
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = c * 64 + lane;
-                        lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+                        const lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
                         const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
-                        float q[DC];
                         uint32_t par = (sbits >> c) & 1u;
     #pragma unroll
                         for (int k = 0; k < DC; ++k) {
-                            q[k] = row[k * Mpad];
-                            par ^= drow[4 * k * Mpad];
+                            qa[c][k] = row[k * S];
+                            par ^= drow[4 * k * S];
                         }
+                        unsat |= par & ((rowv >> c) & 1u);
+                    }
+    #pragma unroll
+                    for (int c = 0; c < PC; ++c) {
+                        const int j = c * 64 + lane;
+                        lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+                        float (&q)[DC] = qa[c];
                         if constexpr (DC == 8) {
                             const int w = (int)cwp[c];
     #pragma unroll
                             for (int k = 2; k < DC; ++k)
                                 if (k >= w) q[k] = 3.402823466e38f;
                         }
-                        unsat |= par & (j < Ml ? 1u : 0u);
                         if constexpr (RULE == kRuleWeighted) {
                             // c->v messages of iteration it + 1 (none after the last)
                             if (it < T) {
                                 lds_f32 *rrow = lds_ptr_f32(ibase_addr + LY::kROff + 4u * (uint32_t)j);
                                 float rp[DC];
     #pragma unroll
-                                for (int k = 0; k < DC; ++k) rp[k] = rrow[k * Mpad];
+                                for (int k = 0; k < DC; ++k) rp[k] = rrow[k * S];
                                 WeightedRule::apply<DC>(q, rp, (int)((sbits >> c) & 1u), w_alpha, w_keep, w_beta,
                                                         rmax);
     #pragma unroll
-                                for (int k = 0; k < DC; ++k) rrow[k * Mpad] = q[k];
+                                for (int k = 0; k < DC; ++k) rrow[k * S] = q[k];
                             }
                         } else {
                             CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
     #pragma unroll
-                            for (int k = 0; k < DC; ++k) row[k * Mpad] = q[k];
+                            for (int k = 0; k < DC; ++k) row[k * S] = q[k];
                         }
                     }
                     const bool sat = __ballot(unsat != 0u) == 0ull;

@@ -44,13 +44,18 @@ struct CheckRule<kRuleNMS> {
         float m1, m2;
         uint32_t sx;
         row_min2<DC>(q, m1, m2, sx);
-        const float A1 = fminf(alpha * m1, rmax);
-        const float A2 = fminf(alpha * m2, rmax);
         const uint32_t sgn = (sx & 0x80000000u) ^ ((uint32_t)sbit << 31);
+        // magnitudes with the row's sign product applied; each slot then flips by its
+        // own sign: sign(q_k) * row product = product over the other slots
+        uint32_t A1s = fbits(fminf(alpha * m1, rmax)) | sgn;
+        uint32_t A2s = fbits(fminf(alpha * m2, rmax)) | sgn;
+        // keep the signed forms as values (one select plus one three-input bit
+        // operation per slot), rather than letting the sign be re-split per slot
+        asm volatile("" : "+v"(A1s), "+v"(A2s));
 #pragma unroll
         for (int k = 0; k < DC; ++k) {
-            const float mag = (fabsf(q[k]) == m1) ? A2 : A1;
-            q[k] = bitsf(fbits(mag) | ((fbits(q[k]) ^ sgn) & 0x80000000u));
+            const uint32_t mag = (fabsf(q[k]) == m1) ? A2s : A1s;
+            q[k] = bitsf((fbits(q[k]) & 0x80000000u) ^ mag);
         }
     }
 };
@@ -170,19 +175,21 @@ struct WeightedRule {
     }
 };
 
-// LDS layout of one BP instance, 64 * PC rows (Mpad) of at most 8 edge slots:
-//   messages  float [8][Mpad]  slot-major: edge (j, k) at k * Mpad + j
-//   decisions u8    [8][Mpad]  stored as 32-bit cells at the message offset + 32 * Mpad,
-//                              so one table address serves both arrays
-//   weighted rule only: c->v messages float [8][Mpad] at + 64 * Mpad (the message
-//                              array then holds the v->c messages only)
+// LDS layout of one BP instance, 64 * PC row positions (Mpad) of at most 8 edge
+// slots, slot stride S = Mpad + kSlotPad words:
+//   messages  float [8][S]  slot-major: edge (p, k) at k * S + p
+//   decisions u8    [8][S]  stored as 32-bit cells at the message offset + 32 * S,
+//                           so one table address serves both arrays
+//   weighted rule only: c->v messages float [8][S] at + 64 * S (the message array
+//                           then holds the v->c messages only)
 //   syndrome words, output staging words, per-shot priors.
-// Rows >= M_l are unused by representation l; row Mmax (of the part) is the sink
-// of absent edges.  Every table entry is a byte address in LDS.
+// Junk positions are unused by representation l; position Mmax (of the part) is the
+// sink of absent edges.  Every table entry is a byte address in LDS.
 template <int PC, int RULE = kRuleNMS>
 struct Layout {
     static constexpr int Mpad = 64 * PC;
-    static constexpr uint32_t kArr = 32u * Mpad;                            // bytes of one [8][Mpad] array
+    static constexpr int S = Mpad + kSlotPad;                              // slot stride (words)
+    static constexpr uint32_t kArr = 32u * S;                              // bytes of one [8][S] array
     static constexpr uint32_t kDecOff = kArr;                               // decisions after the messages
     static constexpr uint32_t kROff = RULE == kRuleWeighted ? 2u * kArr : 0u;  // where c->v messages live
     static constexpr uint32_t kTail = (RULE == kRuleWeighted ? 3u : 2u) * kArr;  // syndrome words start here
@@ -208,8 +215,10 @@ __device__ __forceinline__ float excl_sums(const float (&r)[D], float mu, float 
 // Variable rule (eq. (2) and the posterior of Section II-B) for a variable of
 // degree deg <= D (edges k >= deg point at the sink and read as 0): reads the c->v
 // messages at ea + ROFF, writes every q_k at ea and the hard decision at ea + DECOFF.
+// prev is the decision already stored in the cells: when no lane of the wave changed
+// its decision the cell stores are skipped (must be called by all 64 lanes).
 template <int D, uint32_t DECOFF, uint32_t ROFF>
-__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
+__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, float &P, bool &dec) {
     float r[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -221,9 +230,10 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     dec = pre < 0.0f;
     P = pre;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        *lds_ptr_f32(ea[k]) = q[k];
-        *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+    for (int k = 0; k < D; ++k) *lds_ptr_f32(ea[k]) = q[k];
+    if (__ballot(dec != prev) != 0ull) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
     }
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <climits>
+
 namespace mbbp {
 
 constexpr int kMaxRowWeight = 8;   // row slots per check in LDS (stride 8)
@@ -12,21 +14,30 @@ constexpr int kMaxVarDegree = 8;   // edge slots per variable
 constexpr int kMaxL = 64;
 constexpr int kMaxN = 1024;
 
+// LDS rows of a representation are "positions": check j of representation l sits at
+// position pos_l(j) and owns LDS edge ids pos*8 .. pos*8 + w_j - 1.  Positions run
+// over [0, Mmax); Mmax itself is the sink of absent edges (shared by all
+// representations); positions no check uses are junk (csrc = kJunkRow).
+constexpr int32_t kJunkRow = INT32_MIN;
+// Slot stride of the slot-major LDS arrays: Mpad + kSlotPad words, so the slots of one
+// row fall in different banks.
+constexpr int kSlotPad = 1;
+
 // Tables of one part (one parity-check matrix and its L representations).
-// Check j of representation l owns LDS edge ids j*8 .. j*8 + w_j - 1.
 struct DevPart {
     int m, n, L;
     int W, Ws;          // 64-bit words of n bits / of m bits
-    int Mmax;           // max checks over representations
+    int Mmax;           // positions per representation (the sink is position Mmax)
     int uniform_dc;     // 6 if every row of every representation has weight 6, else 0
     const int32_t *M;   // [L] checks of each representation
     const int32_t *E;   // [L] edges of each representation
     const uint16_t *voff;   // [L][n][8] edge ids of the variable in slot s, ascending check order
     const uint16_t *vid;    // [L][n] variable id of slot s (slots sorted by degree, descending)
     const uint8_t *vdeg;    // [L][n] degree of the variable in slot s
-    const uint8_t *cw;      // [L][Mmax] row weight of check j (0 beyond M_l)
-    const int32_t *csrc;    // [L][Mmax] syndrome source of check j: j < m -> j; duplicate -> H row;
-                            // explicit row -> -(c + 1), combination c in comb_ptr/comb_idx
+    const uint8_t *cw;      // [L][Mmax] row weight at each position (8 at junk positions)
+    const int32_t *csrc;    // [L][Mmax] syndrome source at each position: H row j -> j; duplicate
+                            // of H row r -> r; explicit row -> -(c + 1), combination c in
+                            // comb_ptr/comb_idx; junk position -> kJunkRow
     const int32_t *comb_ptr;
     const int32_t *comb_idx;
     const int32_t *hrow_ptr;   // H in CSR (sampler / failure test)
@@ -34,9 +45,10 @@ struct DevPart {
     const uint64_t *logical;   // [k][W] logical operators of the other type (failure test)
     int k;
     // serial schedule: levels of representation l are lev_ptr[lev_off[l] ..
-    // lev_off[l + 1]) (offsets into lev_chk + l * Mmax, the checks ordered by level);
-    // ltab[(l * Mmax + j) * 8 + k] = 8 x u16: variable id | degree << 12, then the
-    // variable's other edge ids in ascending check order (sink beyond its degree)
+    // lev_off[l + 1]) (offsets into lev_chk + l * Mmax, the positions of the checks
+    // ordered by level); ltab[(l * Mmax + p) * 8 + k] = 8 x u16: variable id | degree
+    // << 12, then the variable's other edge ids in ascending check order (sink beyond
+    // its degree)
     const int32_t *lev_off;
     const int32_t *lev_ptr;
     const uint16_t *lev_chk;

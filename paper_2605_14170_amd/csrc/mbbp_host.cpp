@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/mbbp.h"
+#include "mbbp_layout.h"
 #include "mbbp_device.h"
 
 namespace {
@@ -288,6 +289,9 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
         P.M[l] = (int)reps[l].size();
         P.Mmax = std::max(P.Mmax, P.M[l]);
     }
+    // LDS row positions: the largest representation plus the sink, rounded up to whole
+    // 64-lane passes; position Mmax is the sink, the others are free for the layout
+    P.Mmax = 64 * ((P.Mmax + 1 + 63) / 64) - 1;
     if ((int64_t)(P.Mmax + 1) * 8 > 65535)
         return fail(MBBP_EUNSUPPORTED, std::string(name) + ": too many checks in a representation");
     bool all6 = true;
@@ -299,43 +303,61 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
         }
     P.uniform_dc = all6 ? 6 : 0;
     const int L = bl.L, Mmax = P.Mmax;
-    P.voff.assign((size_t)L * n * 8, 0);
+    const uint16_t sink = (uint16_t)(Mmax * 8);
+    P.voff.assign((size_t)L * n * 8, sink);
     P.vid.assign((size_t)L * n, 0);
     P.vdeg.assign((size_t)L * n, 0);
-    P.cw.assign((size_t)L * Mmax, 0);
-    P.csrc.assign((size_t)L * Mmax, 0);
+    P.cw.assign((size_t)L * Mmax, 8);
+    P.csrc.assign((size_t)L * Mmax, mbbp::kJunkRow);
+    // annealing budget of the bank-aware layout, per representation
+    const long iters = std::min<long>(30L * (n + P.Mmax), 400000L / std::max(1, L));
     for (int l = 0; l < L; ++l) {
+        const int Ml = P.M[l];
+        for (int j = 0; j < Ml; ++j)
+            if ((int)reps[l][j].size() > mbbp::kMaxRowWeight)
+                return fail(MBBP_EUNSUPPORTED, std::string(name) + ": row weight > 8");
+        {
+            std::vector<int> degc(n, 0);
+            for (int j = 0; j < Ml; ++j)
+                for (int v : reps[l][j]) degc[v]++;
+            for (int i = 0; i < n; ++i)
+                if (degc[i] > mbbp::kMaxVarDegree)
+                    return fail(MBBP_EUNSUPPORTED, std::string(name) + ": column weight > 8");
+        }
+        // positions of the checks and lanes of the variables (storage only)
+        mbbp::layout::Result lay;
+        {
+            std::vector<std::vector<int>> rows(Ml);
+            for (int j = 0; j < Ml; ++j) rows[j].assign(reps[l][j].begin(), reps[l][j].end());
+            mbbp::layout::optimize(rows, n, Mmax, 0x5eed0000ull + (uint64_t)l * 7919u + (uint64_t)Mmax, iters,
+                                   lay);
+        }
+        const std::vector<int32_t> &pos = lay.pos;
+        // edges of every variable in ascending check order, as LDS edge ids pos * 8 + slot
         std::vector<std::vector<uint16_t>> vedges(n);
         int E = 0;
-        for (int j = 0; j < P.M[l]; ++j) {
+        for (int j = 0; j < Ml; ++j) {
             const Row &r = reps[l][j];
-            P.cw[(size_t)l * Mmax + j] = (uint8_t)r.size();
-            P.csrc[(size_t)l * Mmax + j] = srcs[l][j];
-            for (size_t k = 0; k < r.size(); ++k) vedges[r[k]].push_back((uint16_t)(j * 8 + k));
+            P.cw[(size_t)l * Mmax + pos[j]] = (uint8_t)r.size();
+            P.csrc[(size_t)l * Mmax + pos[j]] = srcs[l][j];
+            for (size_t k = 0; k < r.size(); ++k) vedges[r[k]].push_back((uint16_t)(pos[j] * 8 + k));
             E += (int)r.size();
         }
         P.E[l] = E;
-        std::vector<int> slot(n);
-        for (int i = 0; i < n; ++i) slot[i] = i;
-        std::stable_sort(slot.begin(), slot.end(),
-                         [&](int a, int b) { return vedges[a].size() > vedges[b].size(); });
         for (int s = 0; s < n; ++s) {
-            const int i = slot[s];
-            if ((int)vedges[i].size() > mbbp::kMaxVarDegree)
-                return fail(MBBP_EUNSUPPORTED, std::string(name) + ": column weight > 8");
+            const int i = lay.slot_var[s];
             P.vid[(size_t)l * n + s] = (uint16_t)i;
             P.vdeg[(size_t)l * n + s] = (uint8_t)vedges[i].size();
-            for (int k = 0; k < 8; ++k)  // absent edges point at the sink row
-                P.voff[((size_t)l * n + s) * 8 + k] =
-                    k < (int)vedges[i].size() ? vedges[i][k] : (uint16_t)(Mmax * 8);
+            for (int k = 0; k < (int)vedges[i].size(); ++k)  // absent edges point at the sink
+                P.voff[((size_t)l * n + s) * 8 + k] = vedges[i][k];
         }
         // Serial schedule (Section II-B): checks are visited in row order, each seeing
         // the latest check messages.  Level of check j = 1 + the highest level of an
         // earlier check sharing a variable with it; checks of one level share no
         // variable, so running levels in order equals the row-order sweep exactly.
-        std::vector<int> lastlev(n, -1), level(P.M[l], 0);
+        std::vector<int> lastlev(n, -1), level(Ml, 0);
         int nlev = 0;
-        for (int j = 0; j < P.M[l]; ++j) {
+        for (int j = 0; j < Ml; ++j) {
             int lv = 0;
             for (int v : reps[l][j]) lv = std::max(lv, lastlev[v] + 1);
             level[j] = lv;
@@ -343,30 +365,32 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             nlev = std::max(nlev, lv + 1);
         }
         std::vector<int> cnt(nlev + 1, 0);
-        for (int j = 0; j < P.M[l]; ++j) cnt[level[j] + 1]++;
+        for (int j = 0; j < Ml; ++j) cnt[level[j] + 1]++;
         for (int t = 0; t < nlev; ++t) cnt[t + 1] += cnt[t];
         for (int t = 0; t <= nlev; ++t) P.lev_ptr.push_back(cnt[t]);
         P.lev_off.push_back((int32_t)P.lev_ptr.size());
         std::vector<uint16_t> order(Mmax, 0);
         {
             std::vector<int> fill(cnt.begin(), cnt.end() - 1);
-            for (int j = 0; j < P.M[l]; ++j) order[fill[level[j]]++] = (uint16_t)j;
+            for (int j = 0; j < Ml; ++j) order[fill[level[j]]++] = (uint16_t)pos[j];
         }
         P.lev_chk.insert(P.lev_chk.end(), order.begin(), order.end());
-        // per check slot (j, k): word 0 = variable id | degree << 12, words 1..7 = the
-        // variable's other edges in ascending check order (sink beyond its degree)
-        std::vector<uint16_t> tab((size_t)Mmax * 8 * 8, (uint16_t)(Mmax * 8));
-        for (int j = 0; j < Mmax; ++j)
-            for (int k = 0; k < 8; ++k) tab[((size_t)j * 8 + k) * 8] = 0;
-        for (int j = 0; j < P.M[l]; ++j) {
+        // per check slot (position p, k): word 0 = variable id | degree << 12, words
+        // 1..7 = the variable's other edges in ascending check order (sink beyond its
+        // degree)
+        std::vector<uint16_t> tab((size_t)Mmax * 8 * 8, sink);
+        for (int p = 0; p < Mmax; ++p)
+            for (int k = 0; k < 8; ++k) tab[((size_t)p * 8 + k) * 8] = 0;
+        for (int j = 0; j < Ml; ++j) {
             const Row &r = reps[l][j];
             for (size_t k = 0; k < r.size(); ++k) {
                 const int v = r[k];
-                uint16_t *e = &tab[((size_t)j * 8 + k) * 8];
+                const uint16_t self = (uint16_t)(pos[j] * 8 + k);
+                uint16_t *e = &tab[(size_t)self * 8];
                 e[0] = (uint16_t)(v | ((int)vedges[v].size() << 12));
                 int t = 1;
                 for (uint16_t other : vedges[v])
-                    if (other != (uint16_t)(j * 8 + k)) e[t++] = other;
+                    if (other != self) e[t++] = other;
             }
         }
         P.ltab.insert(P.ltab.end(), tab.begin(), tab.end());
@@ -497,9 +521,9 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
 }
 
 // LDS bytes of one BP instance (must match bp_wave_kernel): messages and decision
-// cells for Mpad rows of 8 slots (64 * Mpad bytes; the weighted rule adds the c->v
-// messages, 32 * Mpad bytes), the syndrome words, the output staging words and, for
-// per-shot priors, the shot's n priors.
+// cells for 8 slots of stride Mpad + kSlotPad words (64 * stride bytes; the weighted
+// rule adds the c->v messages, 32 * stride bytes), the syndrome words, the output
+// staging words and, for per-shot priors, the shot's n priors.
 bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, int rule,
                  mbbp::BPArgs &a) {
     int W = 0, Ws = 0, n = 0;
@@ -513,13 +537,14 @@ bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, 
     a.ws_max = Ws;
     a.w_max = W;
     a.n_max = n;
-    a.msg_bytes = 32 * mpad;
-    a.zero_bytes = 64 * mpad;
+    const int stride = mpad + mbbp::kSlotPad;  // slot stride of the LDS arrays (words)
+    a.msg_bytes = 32 * stride;
+    a.zero_bytes = 64 * stride;
     // serial schedule: priors always staged (n floats) plus one syndrome byte per row
     const bool serial = schedule == MBBP_LAYERED;
-    // the weighted rule keeps the c->v messages in a third [8][Mpad] array
+    // the weighted rule keeps the c->v messages in a third [8][stride] array
     const int arrays = rule == MBBP_WEIGHTED ? 3 : 2;
-    const int bytes = arrays * 32 * mpad + Ws * 8 + W * 8 + ((per_shot_prior || serial) ? n * 4 : 0) +
+    const int bytes = arrays * 32 * stride + Ws * 8 + W * 8 + ((per_shot_prior || serial) ? n * 4 : 0) +
                       (serial ? mpad : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     return true;
@@ -1287,7 +1312,7 @@ mbbp_status mbbp_wbp_ckpt_floats(mbbp_ctx *ctx, int32_t part, int64_t shots, int
     const float one = 0.0f;
     mbbp_status st = wbp_common(ctx, part, shots, &one, &one, &one, &one, ckpt_every, n_ck, mpad);
     if (st != MBBP_OK) return st;
-    *floats = shots * (int64_t)ctx->dp[part].L * n_ck * 8 * mpad;
+    *floats = shots * (int64_t)ctx->dp[part].L * n_ck * 8 * (mpad + mbbp::kSlotPad);
     return MBBP_OK;
 }
 
@@ -1345,7 +1370,7 @@ mbbp_status mbbp_wbp_backward(mbbp_ctx *ctx, int32_t part, int64_t shots, const 
     a.grad_llr = grad_llr;
     a.ws = D.Ws;
     a.n = D.n;
-    const int bytes = (3 + ckpt_every) * 32 * mpad + D.Ws * 8 + (prior_per_shot ? D.n * 4 : 0);
+    const int bytes = (3 + ckpt_every) * 32 * (mpad + mbbp::kSlotPad) + D.Ws * 8 + (prior_per_shot ? D.n * 4 : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     int wpb = 4;
     while (wpb > 1 && (size_t)wpb * a.inst_bytes > mbbp::bp_lds_limit()) wpb /= 2;

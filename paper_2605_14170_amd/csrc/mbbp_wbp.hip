@@ -14,7 +14,7 @@
 // functions), so gradients do not depend on the checkpoint interval.
 //
 // One instance per wavefront, the decoding kernel's table layout.  LDS per
-// instance (A = one [8][Mpad] float array): Q (v->c messages) at 0, RB (adjoint
+// instance (A = one [8][S] float array, S the slot stride): Q (v->c messages) at 0, RB (adjoint
 // of c->v messages) at A, QB (adjoint of v->c messages) at 2A, the segment's
 // c->v messages R[0..ckpt_every) at 3A, then syndrome words and per-shot priors.
 #include <hip/hip_runtime.h>
@@ -82,8 +82,8 @@ __device__ __forceinline__ void var_phase(const uint32_t (&ea)[PV][kMaxVarDegree
 
 template <int PV, int PC, int DC>
 __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
-    constexpr int Mpad = 64 * PC;
-    constexpr uint32_t A = 32u * Mpad;
+    constexpr int S = 64 * PC + kSlotPad;  // slot stride of the LDS arrays (words)
+    constexpr uint32_t A = 32u * S;
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
@@ -98,8 +98,7 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
     const int l = (int)(item / a.shots);
     const int64_t shot = item - (int64_t)l * a.shots;
     const DevPart *pt = a.dpart;
-    const int n = pt->n, m = pt->m, Mmax = pt->Mmax, Ws = pt->Ws, L = pt->L;
-    const int Ml = pt->M[l];
+    const int n = pt->n, Mmax = pt->Mmax, Ws = pt->Ws, L = pt->L;
     const int vp = (n + 63) >> 6;
     const size_t inst = (size_t)shot * L + l;
     const float rmax = a.rmax;
@@ -131,7 +130,7 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
 #pragma unroll
             for (int k = 0; k < kMaxVarDegree; ++k) {
                 const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-                ea[v][k] = ibase_addr + 4u * ((e & 7u) * (uint32_t)Mpad + (e >> 3));
+                ea[v][k] = ibase_addr + 4u * ((e & 7u) * (uint32_t)S + (e >> 3));
             }
             vinfo[v] = id | ((uint32_t)deg << 16) | (valid ? 0x80000000u : 0u);
             dmaxp[v] = uniform_i32(wave_max_i32(deg));
@@ -140,7 +139,7 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
 #pragma unroll
         for (int c = 0; c < PC; ++c) {
             const int j = c * 64 + lane;
-            cwp[c] = (DC == 8 && j < Ml) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
+            cwp[c] = (DC == 8 && j < Mmax) ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
         }
     }
     // clear Q, RB, QB and the segment arrays; stage the syndrome and priors
@@ -157,14 +156,15 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
 #pragma unroll
         for (int v = 0; v < PV; ++v) mu[v] = (vinfo[v] >> 31) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
     }
-    uint32_t sbits = 0;
+    uint32_t sbits = 0, rowv = 0;  // syndrome bit and "real check" flag per pass
     {
         const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
 #pragma unroll
         for (int c = 0; c < PC; ++c) {
             const int j = c * 64 + lane;
-            if (j < Ml) {
-                const int src = j < m ? j : csrc[j];
+            const int src = j < Mmax ? csrc[j] : kJunkRow;
+            if (src != kJunkRow) {
+                rowv |= 1u << c;
                 uint32_t bit = 0;
                 if (src >= 0) {
                     bit = (uint32_t)(synl[src >> 6] >> (src & 63)) & 1u;
@@ -198,11 +198,11 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
         {
             uint4 *r0 = reinterpret_cast<uint4 *>(ibase + 3u * A);
             if (t0 == 0) {
-                for (int i = lane; i < 2 * Mpad; i += 64) r0[i] = make_uint4(0u, 0u, 0u, 0u);
+                for (int i = lane; i < 2 * S; i += 64) r0[i] = make_uint4(0u, 0u, 0u, 0u);
             } else {
                 const uint4 *src =
-                    reinterpret_cast<const uint4 *>(a.ckpt + (inst * a.n_ck + (size_t)(seg - 1)) * (8 * Mpad));
-                for (int i = lane; i < 2 * Mpad; i += 64) r0[i] = src[i];
+                    reinterpret_cast<const uint4 *>(a.ckpt + (inst * a.n_ck + (size_t)(seg - 1)) * (8 * S));
+                for (int i = lane; i < 2 * S; i += 64) r0[i] = src[i];
             }
         }
         wave_sync();
@@ -221,14 +221,14 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
                 float q[DC], rp[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    q[k] = qrow[k * Mpad];
-                    rp[k] = rrow[k * Mpad];
+                    q[k] = qrow[k * S];
+                    rp[k] = rrow[k * S];
                     if (DC == 8 && k >= 2 && k >= (int)cwp[c]) q[k] = 3.402823466e38f;
                 }
                 WeightedRule::apply<DC>(q, rp, (int)((sbits >> c) & 1u), al, keep, be, rmax);
                 lds_f32 *orow = lds_ptr_f32(ibase_addr + rnew + 4u * (uint32_t)j);
 #pragma unroll
-                for (int k = 0; k < DC; ++k) orow[k * Mpad] = q[k];
+                for (int k = 0; k < DC; ++k) orow[k * S] = q[k];
             }
             wave_sync();
         }
@@ -250,9 +250,9 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
                 float q[DC], rp[DC], rb[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    q[k] = qrow[k * Mpad];
-                    rp[k] = rrow[k * Mpad];
-                    rb[k] = rbrow[k * Mpad];
+                    q[k] = qrow[k * S];
+                    rp[k] = rrow[k * S];
+                    rb[k] = rbrow[k * S];
                     if (DC == 8 && k >= 2 && k >= (int)cwp[c]) {
                         q[k] = 3.402823466e38f;
                         rb[k] = 0.0f;
@@ -262,14 +262,14 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
                 float gal = 0.0f, gbl = 0.0f;
                 WeightedRule::adjoint<DC>(q, rp, rb, (int)((sbits >> c) & 1u), al, keep, be, rmax, rbp, qb, gal,
                                           gbl);
-                if (j < Ml) {
+                if ((rowv >> c) & 1u) {
                     ga += gal;
                     gb += gbl;
                 }
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    rbrow[k * Mpad] = rbp[k];
-                    qbrow[k * Mpad] = qb[k];
+                    rbrow[k * S] = rbp[k];
+                    qbrow[k * S] = qb[k];
                 }
             }
             wave_sync();
