@@ -93,6 +93,13 @@ void bp_wave_kernel(BPArgs a) {
     int dmaxp[PV];                   // max degree of pass v (wave-uniform)
     uint32_t cwp[PC];                // row weights (DC == 8 only)
     float mu[PV];
+    int32_t csrcp[PC];               // syndrome source of each check position (kJunkRow: none)
+    // flooding min-sum / sum-product start every shot from stores only (iteration 0
+    // needs no c->v message), so the LDS arrays are cleared only when a wave takes up
+    // a representation; the weighted rule (damping reads r^(0) = 0) and the serial
+    // schedule (posteriors read c->v messages) clear them for every shot
+    constexpr bool kClearPerShot = RULE == kRuleWeighted || SCHED == 1;
+    bool clear_now = true;
 
     while (item < a.n_items) {
         const ItemPos ip = decode_item(a, item);
@@ -142,20 +149,29 @@ void bp_wave_kernel(BPArgs a) {
                     cwp[c] = j < Mmax ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
                 }
             }
+            const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
+#pragma unroll
+            for (int c = 0; c < PC; ++c) {
+                const int j = c * 64 + lane;
+                csrcp[c] = j < Mmax ? csrc[j] : kJunkRow;
+            }
+            clear_now = true;
         }
         const float *prior = pick(a.prior, ip.part);
         const uint64_t *syn = pick(a.syn, ip.part);
         uint64_t *cand = pick(a.cand, ip.part);
         uint16_t *kstat = pick(a.kstat, ip.part);
         float *llr = pick(a.llr, ip.part);
-        const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
 
         for (int64_t shot = ip.begin; shot < ip.end; ++shot) {
             // ---------------- fill: clear messages and decisions, stage syndrome (and priors)
             {
-                uint4 *z = reinterpret_cast<uint4 *>(ibase);
-                constexpr int nz = (int)(LY::kTail / 16);
-                for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+                if (kClearPerShot || clear_now) {
+                    uint4 *z = reinterpret_cast<uint4 *>(ibase);
+                    constexpr int nz = (int)(LY::kTail / 16);
+                    for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+                    clear_now = false;
+                }
                 if (lane < Ws) synl[lane] = syn[shot * Ws + lane];
                 if (a.prior_per_shot || kMuLds) {
                     const float *pr = prior + (a.prior_per_shot ? shot * n : 0);
@@ -174,7 +190,7 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
             for (int c = 0; c < PC; ++c) {
                 const int j = c * 64 + lane;
-                const int src = j < Mmax ? csrc[j] : kJunkRow;
+                const int src = csrcp[c];
                 if (src != kJunkRow) {
                     rowv |= 1u << c;
                     uint32_t bit = 0;
@@ -301,6 +317,19 @@ void bp_wave_kernel(BPArgs a) {
                             float Pv = 0.0f;
                             bool d = false;
                             const bool prevd = (decb >> v) & 1u;
+                            if (!kClearPerShot && it == 0) {
+                                switch (uniform_i32(dmaxp[v])) {
+                                case 1: var_first<1, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 2: var_first<2, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 3: var_first<3, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 4: var_first<4, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 5: var_first<5, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 6: var_first<6, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 7: var_first<7, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 8: var_first<8, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                default: Pv = mu[v]; d = Pv < 0.0f; break;
+                                }
+                            } else {
                             switch (uniform_i32(dmaxp[v])) {
                             case 1: var_rule<1, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
                             case 2: var_rule<2, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
@@ -311,6 +340,7 @@ void bp_wave_kernel(BPArgs a) {
                             case 7: var_rule<7, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
                             case 8: var_rule<8, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
+                            }
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
                             if (llr && (!a.fixed_T || it == T)) {

@@ -237,6 +237,20 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     }
 }
 
+// Variable rule at iteration 0 of the flooding schedule, where every c->v message is
+// 0: q_k = P = mu (stored as-is; mu is canonical, never -0), and every decision cell
+// is written, so nothing left from an earlier shot is read later.
+template <int D, uint32_t DECOFF>
+__device__ __forceinline__ void var_first(const uint32_t *ea, float mu, float &P, bool &dec) {
+    dec = mu < 0.0f;
+    P = mu;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        *lds_ptr_f32(ea[k]) = mu;
+        *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+    }
+}
+
 // Posterior only (serial schedule): P = mu + sum r in ascending check order and the
 // hard decision written to every edge's decision cell; messages are left alone.
 template <int D, uint32_t DECOFF>
