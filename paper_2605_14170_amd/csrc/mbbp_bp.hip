@@ -209,6 +209,9 @@ void bp_wave_kernel(BPArgs a) {
             int it = 0, kfix = -1, K = T;
             bool conv = false;
             uint32_t decb = 0;
+            float Pl[PV];  // posteriors of the last variable phase (written out at the end)
+#pragma unroll
+            for (int v = 0; v < PV; ++v) Pl[v] = 0.0f;
             if constexpr (SCHED == 1) {
                 const int32_t *lp = pt->lev_ptr + pt->lev_off[l];
                 const int nlev = pt->lev_off[l + 1] - pt->lev_off[l] - 1;
@@ -234,10 +237,7 @@ void bp_wave_kernel(BPArgs a) {
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                            if (llr) {
-                                const int s = v * 64 + lane;
-                                if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
-                            }
+                            Pl[v] = Pv;
                         }
                     }
                     wave_sync();
@@ -343,10 +343,7 @@ void bp_wave_kernel(BPArgs a) {
                             }
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                            if (llr && (!a.fixed_T || it == T)) {
-                                const int s = v * 64 + lane;
-                                if (s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pv;
-                            }
+                            Pl[v] = Pv;
                         }
                     }
                     wave_sync();
@@ -417,6 +414,13 @@ void bp_wave_kernel(BPArgs a) {
                     }
                     ++it;
                     wave_sync();
+                }
+            }
+            if (llr) {
+#pragma unroll
+                for (int v = 0; v < PV; ++v) {
+                    const int s = v * 64 + lane;
+                    if (v < vp && s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pl[v];
                 }
             }
             // ---------------- output: bit-packed hard decisions via the staging words
