@@ -266,8 +266,8 @@ mbbp_status mbbp_set_weights(mbbp_ctx *ctx, const float *alpha, const float *bet
 
 /* Floats of the checkpoint buffer of mbbp_wbp_forward for `shots` shots of one part
  * with a checkpoint every ckpt_every >= 1 iterations:
- * shots * L * (ceil(T / ckpt_every) - 1) * 8 * Mpad, Mpad the kernel's padded row
- * count for that part. */
+ * shots * L * (ceil(T / ckpt_every) - 1) * 8 * S, S the kernel's slot stride for that
+ * part. */
 mbbp_status mbbp_wbp_ckpt_floats(mbbp_ctx *ctx, int32_t part, int64_t shots, int32_t ckpt_every, int64_t *floats);
 
 /* Training forward of one part: weighted min-sum for exactly T iterations (no early
@@ -292,7 +292,8 @@ mbbp_status mbbp_wbp_forward(mbbp_ctx *ctx, int32_t part, int64_t shots, const u
  * strictly inside (-r_max, r_max).  Per-instance partial sums are added over shots
  * in FP64 in a fixed order: results are deterministic.
  * Limits (MBBP_EUNSUPPORTED): n <= 320 and at most 319 checks per representation;
- * (3 + ckpt_every) * 32 * Mpad bytes of LDS per instance must fit 64 KiB. */
+ * (3 + ckpt_every) * 32 * S bytes of LDS per instance (S the slot stride) must fit
+ * 64 KiB. */
 mbbp_status mbbp_wbp_backward(mbbp_ctx *ctx, int32_t part, int64_t shots, const uint64_t *syn, const float *prior,
                               int32_t prior_per_shot, const float *alpha, const float *beta, int32_t ckpt_every,
                               const float *ckpt, const float *grad_llr, float *grad_alpha, float *grad_beta,
