@@ -61,7 +61,7 @@ __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 
 template <int PV, int PC, int DC, int RULE, int SCHED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : 1)))
 void bp_wave_kernel(BPArgs a) {
-    using LY = Layout<PC, RULE>;
+    using LY = Layout<PC, RULE, DC>;
     static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
     constexpr int S = LY::S;  // slot stride of the LDS arrays (words)
     const int lane = threadIdx.x & 63;
@@ -70,6 +70,7 @@ void bp_wave_kernel(BPArgs a) {
     unsigned char *ibase = smem + (size_t)wib * a.inst_bytes;
     const uint32_t ibase_addr = (uint32_t)(size_t)(lds_u8 *)ibase;
     uint64_t *synl = reinterpret_cast<uint64_t *>(ibase + LY::kTail);
+    const uint32_t dconst = ibase_addr + LY::kDecOff - (ibase_addr >> 2);  // decision cell addressing
     uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
     float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
     unsigned char *sbl = reinterpret_cast<unsigned char *>(mul + a.n_max);  // serial: syndrome byte per check
@@ -226,14 +227,14 @@ void bp_wave_kernel(BPArgs a) {
                             float Pv = 0.0f;
                             bool d = false;
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_post<1, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 2: var_post<2, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 3: var_post<3, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 4: var_post<4, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 5: var_post<5, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 6: var_post<6, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 7: var_post<7, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
-                            case 8: var_post<8, LY::kDecOff>(ea[v], deg, mu[v], Pv, d); break;
+                            case 1: var_post<1, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 2: var_post<2, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 3: var_post<3, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 4: var_post<4, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 5: var_post<5, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 6: var_post<6, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 7: var_post<7, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 8: var_post<8, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
@@ -246,10 +247,10 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = c * 64 + lane;
-                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
+                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + LY::kDecMul * (uint32_t)j);
                         uint32_t par = (sbits >> c) & 1u;
 #pragma unroll
-                        for (int k = 0; k < DC; ++k) par ^= drow[4 * k * S];
+                        for (int k = 0; k < DC; ++k) par ^= drow[LY::kDecMul * k * S];
                         unsat |= par & ((rowv >> c) & 1u);
                     }
                     const bool sat = __ballot(unsat != 0u) == 0ull;
@@ -305,8 +306,8 @@ void bp_wave_kernel(BPArgs a) {
                         if (a.ckpt && it > 0 && it < T && it % a.ckpt_every == 0) {
                             const uint4 *src = reinterpret_cast<const uint4 *>(ibase + LY::kROff);
                             uint4 *dst = reinterpret_cast<uint4 *>(
-                                a.ckpt + (((size_t)shot * L + l) * a.n_ck + (it / a.ckpt_every - 1)) * (8 * S));
-                            for (int i = lane; i < 2 * S; i += 64) dst[i] = src[i];
+                                a.ckpt + (((size_t)shot * L + l) * a.n_ck + (it / a.ckpt_every - 1)) * (LY::kMsg / 4));
+                            for (int i = lane; i < (int)(LY::kMsg / 16); i += 64) dst[i] = src[i];
                         }
                     }
                     // ---------------- variable phase
@@ -319,26 +320,26 @@ void bp_wave_kernel(BPArgs a) {
                             const bool prevd = (decb >> v) & 1u;
                             if (!kClearPerShot && it == 0) {
                                 switch (uniform_i32(dmaxp[v])) {
-                                case 1: var_first<1, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 2: var_first<2, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 3: var_first<3, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 4: var_first<4, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 5: var_first<5, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 6: var_first<6, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 7: var_first<7, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
-                                case 8: var_first<8, LY::kDecOff>(ea[v], mu[v], Pv, d); break;
+                                case 1: var_first<1, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 2: var_first<2, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 3: var_first<3, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 4: var_first<4, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 5: var_first<5, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 6: var_first<6, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 7: var_first<7, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 8: var_first<8, LY>(ea[v], mu[v], dconst, Pv, d); break;
                                 default: Pv = mu[v]; d = Pv < 0.0f; break;
                                 }
                             } else {
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_rule<1, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 2: var_rule<2, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 3: var_rule<3, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 4: var_rule<4, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 5: var_rule<5, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 6: var_rule<6, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 7: var_rule<7, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 8: var_rule<8, LY::kDecOff, LY::kROff>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 1: var_rule<1, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 2: var_rule<2, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 3: var_rule<3, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 4: var_rule<4, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 5: var_rule<5, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 6: var_rule<6, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 7: var_rule<7, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 8: var_rule<8, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             }
@@ -365,12 +366,12 @@ void bp_wave_kernel(BPArgs a) {
                     for (int c = 0; c < PC; ++c) {
                         const int j = c * 64 + lane;
                         const lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
-                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + 4u * (uint32_t)j);
+                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + LY::kDecMul * (uint32_t)j);
                         uint32_t par = (sbits >> c) & 1u;
     #pragma unroll
                         for (int k = 0; k < DC; ++k) {
                             qa[c][k] = row[k * S];
-                            par ^= drow[4 * k * S];
+                            par ^= drow[LY::kDecMul * k * S];
                         }
                         unsat |= par & ((rowv >> c) & 1u);
                     }

@@ -175,24 +175,35 @@ struct WeightedRule {
     }
 };
 
-// LDS layout of one BP instance, 64 * PC row positions (Mpad) of at most 8 edge
-// slots, slot stride S = Mpad + kSlotPad words:
-//   messages  float [8][S]  slot-major: edge (p, k) at k * S + p
-//   decisions u8    [8][S]  stored as 32-bit cells at the message offset + 32 * S,
-//                           so one table address serves both arrays
-//   weighted rule only: c->v messages float [8][S] at + 64 * S (the message array
-//                           then holds the v->c messages only)
+// LDS layout of one BP instance, 64 * PC row positions (Mpad), slot stride
+// S = Mpad + kSlotPad words.  Two forms: the wide one (8 slots, one 32-bit cell per
+// decision at a fixed offset from the message, so a message's address plus an
+// immediate reaches its decision) and, for large codes whose instances would
+// otherwise leave most of a CU idle for want of LDS, the compact one (DC slots, one
+// byte per decision at (message address >> 2) + dconst):
+//   messages  float [slots][S]  slot-major: edge (p, k) at k * S + p
+//   decisions [slots][S]        cells of kDecMul bytes
+//   weighted rule only: c->v messages float [slots][S] (the message array then holds
+//                               the v->c messages only)
 //   syndrome words, output staging words, per-shot priors.
 // Junk positions are unused by representation l; position Mmax (of the part) is the
 // sink of absent edges.  Every table entry is a byte address in LDS.
-template <int PC, int RULE = kRuleNMS>
+template <int PC, int RULE = kRuleNMS, int DC = 8>
 struct Layout {
+    static constexpr bool kCompact = PC >= 9;
+    static constexpr int kSlots = kCompact ? DC : 8;
     static constexpr int Mpad = 64 * PC;
-    static constexpr int S = Mpad + kSlotPad;                              // slot stride (words)
-    static constexpr uint32_t kArr = 32u * S;                              // bytes of one [8][S] array
-    static constexpr uint32_t kDecOff = kArr;                               // decisions after the messages
-    static constexpr uint32_t kROff = RULE == kRuleWeighted ? 2u * kArr : 0u;  // where c->v messages live
-    static constexpr uint32_t kTail = (RULE == kRuleWeighted ? 3u : 2u) * kArr;  // syndrome words start here
+    static constexpr int S = Mpad + kSlotPad;                                   // slot stride (words)
+    static constexpr uint32_t kMsg = (4u * kSlots * S + 15u) & ~15u;            // bytes of a message array
+    static constexpr uint32_t kDecMul = kCompact ? 1u : 4u;                     // bytes per decision cell
+    static constexpr uint32_t kDec = (kDecMul * kSlots * S + 15u) & ~15u;       // bytes of the decisions
+    static constexpr uint32_t kDecOff = kMsg;                                   // decisions after the messages
+    static constexpr uint32_t kROff = RULE == kRuleWeighted ? kMsg + kDec : 0u;  // where c->v messages live
+    static constexpr uint32_t kTail = kMsg + kDec + (RULE == kRuleWeighted ? kMsg : 0u);  // syndrome words
+    // byte address of the decision cell of the edge whose message is at byte address ea
+    __device__ __forceinline__ static uint32_t dec(uint32_t ea, uint32_t dconst) {
+        return kCompact ? (ea >> 2) + dconst : ea + kDecOff;
+    }
 };
 
 // Exclusion sums of a variable of degree <= D with incoming messages r (unused
@@ -217,8 +228,10 @@ __device__ __forceinline__ float excl_sums(const float (&r)[D], float mu, float 
 // messages at ea + ROFF, writes every q_k at ea and the hard decision at ea + DECOFF.
 // prev is the decision already stored in the cells: when no lane of the wave changed
 // its decision the cell stores are skipped (must be called by all 64 lanes).
-template <int D, uint32_t DECOFF, uint32_t ROFF>
-__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, float &P, bool &dec) {
+template <int D, typename LY>
+__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, uint32_t dconst, float &P,
+                                         bool &dec) {
+    constexpr uint32_t ROFF = LY::kROff;
     float r[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -233,28 +246,28 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     for (int k = 0; k < D; ++k) *lds_ptr_f32(ea[k]) = q[k];
     if (__ballot(dec != prev) != 0ull) {
 #pragma unroll
-        for (int k = 0; k < D; ++k) *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+        for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k], dconst)) = (unsigned char)dec;
     }
 }
 
 // Variable rule at iteration 0 of the flooding schedule, where every c->v message is
 // 0: q_k = P = mu (stored as-is; mu is canonical, never -0), and every decision cell
 // is written, so nothing left from an earlier shot is read later.
-template <int D, uint32_t DECOFF>
-__device__ __forceinline__ void var_first(const uint32_t *ea, float mu, float &P, bool &dec) {
+template <int D, typename LY>
+__device__ __forceinline__ void var_first(const uint32_t *ea, float mu, uint32_t dconst, float &P, bool &dec) {
     dec = mu < 0.0f;
     P = mu;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         *lds_ptr_f32(ea[k]) = mu;
-        *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+        *lds_ptr_u8(LY::dec(ea[k], dconst)) = (unsigned char)dec;
     }
 }
 
 // Posterior only (serial schedule): P = mu + sum r in ascending check order and the
 // hard decision written to every edge's decision cell; messages are left alone.
-template <int D, uint32_t DECOFF>
-__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
+template <int D, typename LY>
+__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, uint32_t dconst, float &P, bool &dec) {
     float pre = mu;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -264,7 +277,7 @@ __device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, 
     dec = pre < 0.0f;
     P = pre;
 #pragma unroll
-    for (int k = 0; k < D; ++k) *lds_ptr_u8(ea[k] + DECOFF) = (unsigned char)dec;
+    for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k], dconst)) = (unsigned char)dec;
 }
 
 }  // namespace mbbp

@@ -520,10 +520,25 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
     return MBBP_OK;
 }
 
-// LDS bytes of one BP instance (must match bp_wave_kernel): messages and decision
-// cells for 8 slots of stride Mpad + kSlotPad words (64 * stride bytes; the weighted
-// rule adds the c->v messages, 32 * stride bytes), the syndrome words, the output
-// staging words and, for per-shot priors, the shot's n priors.
+// Row slots the BP kernel is instantiated with for these parts: 6 when every row of
+// every representation has weight 6, else 8 (must match the kernel launcher).
+int launch_dc(const mbbp_ctx *c, int part0, int nparts) {
+    bool u6 = true;
+    for (int p = part0; p < part0 + nparts; ++p) u6 = u6 && c->dp[p].uniform_dc == 6;
+    return u6 ? 6 : 8;
+}
+
+// Slots per LDS row (must match Layout in mbbp_bp_rules.h): the compact layout of
+// large codes (64 * kCompactPC positions or more) keeps the row weight, the wide one 8.
+constexpr int kCompactPC = 9;
+int lds_slots(const mbbp_ctx *c, int part0, int nparts, int mpad) {
+    return mpad >= 64 * kCompactPC ? launch_dc(c, part0, nparts) : 8;
+}
+
+// LDS bytes of one BP instance (must match Layout in mbbp_bp_rules.h): messages
+// (DC slots of stride Mpad + kSlotPad words, 16-byte rounded), decision bytes, for
+// the weighted rule the c->v messages, the syndrome words, the output staging words
+// and, for per-shot priors or the serial schedule, the shot's n priors.
 bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, int rule,
                  mbbp::BPArgs &a) {
     int W = 0, Ws = 0, n = 0;
@@ -538,14 +553,16 @@ bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, 
     a.w_max = W;
     a.n_max = n;
     const int stride = mpad + mbbp::kSlotPad;  // slot stride of the LDS arrays (words)
-    a.msg_bytes = 32 * stride;
-    a.zero_bytes = 64 * stride;
+    const int slots = lds_slots(c, part0, nparts, mpad);
+    const int cell = mpad >= 64 * kCompactPC ? 1 : 4;  // bytes per decision cell
+    const int msg = (4 * slots * stride + 15) & ~15, dec = (cell * slots * stride + 15) & ~15;
+    a.msg_bytes = msg;
+    a.zero_bytes = msg + dec;
     // serial schedule: priors always staged (n floats) plus one syndrome byte per row
     const bool serial = schedule == MBBP_LAYERED;
-    // the weighted rule keeps the c->v messages in a third [8][stride] array
-    const int arrays = rule == MBBP_WEIGHTED ? 3 : 2;
-    const int bytes = arrays * 32 * stride + Ws * 8 + W * 8 + ((per_shot_prior || serial) ? n * 4 : 0) +
-                      (serial ? mpad : 0);
+    // the weighted rule keeps the c->v messages in a second message array
+    const int bytes = msg + dec + (rule == MBBP_WEIGHTED ? msg : 0) + Ws * 8 + W * 8 +
+                      ((per_shot_prior || serial) ? n * 4 : 0) + (serial ? mpad : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     return true;
 }
@@ -1312,7 +1329,8 @@ mbbp_status mbbp_wbp_ckpt_floats(mbbp_ctx *ctx, int32_t part, int64_t shots, int
     const float one = 0.0f;
     mbbp_status st = wbp_common(ctx, part, shots, &one, &one, &one, &one, ckpt_every, n_ck, mpad);
     if (st != MBBP_OK) return st;
-    *floats = shots * (int64_t)ctx->dp[part].L * n_ck * 8 * (mpad + mbbp::kSlotPad);
+    const int msg = (4 * lds_slots(ctx, part, 1, mpad) * (mpad + mbbp::kSlotPad) + 15) & ~15;
+    *floats = shots * (int64_t)ctx->dp[part].L * n_ck * (msg / 4);
     return MBBP_OK;
 }
 
@@ -1370,7 +1388,8 @@ mbbp_status mbbp_wbp_backward(mbbp_ctx *ctx, int32_t part, int64_t shots, const 
     a.grad_llr = grad_llr;
     a.ws = D.Ws;
     a.n = D.n;
-    const int bytes = (3 + ckpt_every) * 32 * (mpad + mbbp::kSlotPad) + D.Ws * 8 + (prior_per_shot ? D.n * 4 : 0);
+    const int msg = (4 * lds_slots(ctx, part, 1, mpad) * (mpad + mbbp::kSlotPad) + 15) & ~15;
+    const int bytes = (3 + ckpt_every) * msg + D.Ws * 8 + (prior_per_shot ? D.n * 4 : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     int wpb = 4;
     while (wpb > 1 && (size_t)wpb * a.inst_bytes > mbbp::bp_lds_limit()) wpb /= 2;

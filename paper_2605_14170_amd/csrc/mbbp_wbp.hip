@@ -14,7 +14,7 @@
 // functions), so gradients do not depend on the checkpoint interval.
 //
 // One instance per wavefront, the decoding kernel's table layout.  LDS per
-// instance (A = one [8][S] float array, S the slot stride): Q (v->c messages) at 0, RB (adjoint
+// instance (A = one [DC][S] float array, S the slot stride): Q (v->c messages) at 0, RB (adjoint
 // of c->v messages) at A, QB (adjoint of v->c messages) at 2A, the segment's
 // c->v messages R[0..ckpt_every) at 3A, then syndrome words and per-shot priors.
 #include <hip/hip_runtime.h>
@@ -82,8 +82,9 @@ __device__ __forceinline__ void var_phase(const uint32_t (&ea)[PV][kMaxVarDegree
 
 template <int PV, int PC, int DC>
 __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
-    constexpr int S = 64 * PC + kSlotPad;  // slot stride of the LDS arrays (words)
-    constexpr uint32_t A = 32u * S;
+    using LY = Layout<PC, kRuleNMS, DC>;
+    constexpr int S = LY::S;           // slot stride of the LDS arrays (words)
+    constexpr uint32_t A = LY::kMsg;   // bytes of one [DC][S] float array
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int64_t item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
@@ -198,11 +199,11 @@ __global__ __launch_bounds__(256) void wbp_backward_kernel(WBPBackArgs a) {
         {
             uint4 *r0 = reinterpret_cast<uint4 *>(ibase + 3u * A);
             if (t0 == 0) {
-                for (int i = lane; i < 2 * S; i += 64) r0[i] = make_uint4(0u, 0u, 0u, 0u);
+                for (int i = lane; i < (int)(A / 16); i += 64) r0[i] = make_uint4(0u, 0u, 0u, 0u);
             } else {
                 const uint4 *src =
-                    reinterpret_cast<const uint4 *>(a.ckpt + (inst * a.n_ck + (size_t)(seg - 1)) * (8 * S));
-                for (int i = lane; i < 2 * S; i += 64) r0[i] = src[i];
+                    reinterpret_cast<const uint4 *>(a.ckpt + (inst * a.n_ck + (size_t)(seg - 1)) * (A / 4));
+                for (int i = lane; i < (int)(A / 16); i += 64) r0[i] = src[i];
             }
         }
         wave_sync();

@@ -493,3 +493,29 @@ def test_autotune_keeps_results(pk):
         np.testing.assert_array_equal(after[k].cpu().numpy(), b0[k], err_msg=k)
         np.testing.assert_array_equal(plain[k].cpu().numpy(), b0[k], err_msg=k)
     dec.close()
+
+
+@pytest.mark.parametrize("factory,L,T,p,shots", [(codes.bb288, 6, 40, 0.04, 80), (codes.qc882, 6, 30, 0.02, 40)])
+def test_nms_large_codes_bit_exact(pk, factory, L, T, p, shots):
+    """Codes whose representations need 5 or 14 passes of 64 lanes (the latter in the
+    compact LDS layout, one byte per decision): bit-exact against the FP32 oracle."""
+    from workloads.perms import check_permutations
+    code = factory()
+    bx = oracle.build_bases(code.hx, "ramp", L, check_permutations(code.hx.shape[0], L, 3))
+    bz = oracle.build_bases(code.hz, "ramp", L, check_permutations(code.hz.shape[0], L, 3))
+    say(f"large code {code.name}: n={code.n} L={L} T={T} shots={shots}")
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, T, alpha=0.875, max_batch=shots)
+    ex, ez, sx, sz = dec.sample(11, p, 0, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+        torch.cuda.synchronize()
+        ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), T, alpha=0.875, want_llr=True,
+                            precision="f32")
+        ks = kstat.cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(words(cand), ref.cand)
+        np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+        say(f"  part {part}: mean K {ref.K.mean():.2f}")
+    dec.close()
