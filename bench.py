@@ -63,13 +63,17 @@ def parse():
     return ap.parse_args()
 
 
+# sources of the BP kernel; the recorded HBM traffic holds only for these as profiled
+KERNEL_SOURCES = ("mbbp_bp.hip", "mbbp_bp_rules.h", "mbbp_device.h", "mbbp_wave.h")
+
+
 def recorded_traffic(workload, shots_per_launch):
     """HBM bytes per BP launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary, or None when that summary was taken on another BP kernel source or
     another launch size."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"bp_wave_kernel_{workload}.md")
-    src = os.path.join(ROOT, "paper_2605_14170_amd", "csrc", "mbbp_bp.hip")
+    csrc = os.path.join(ROOT, "paper_2605_14170_amd", "csrc")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -78,7 +82,10 @@ def recorded_traffic(workload, shots_per_launch):
             key, _, val = line.partition(":")
             fields[key.strip()] = val.split()[0] if val.split() else ""
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        sha = h.hexdigest()
         if fields.get("kernel_source_sha256") != sha or int(fields.get("shots_per_launch", -1)) != shots_per_launch:
             return None
         return float(fields["bp_kernel_hbm_bytes_per_launch"])
