@@ -70,7 +70,6 @@ void bp_wave_kernel(BPArgs a) {
     unsigned char *ibase = smem + (size_t)wib * a.inst_bytes;
     const uint32_t ibase_addr = (uint32_t)(size_t)(lds_u8 *)ibase;
     uint64_t *synl = reinterpret_cast<uint64_t *>(ibase + LY::kTail);
-    const uint32_t dconst = ibase_addr + LY::kDecOff - (ibase_addr >> 2);  // decision cell addressing
     uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
     float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
     unsigned char *sbl = reinterpret_cast<unsigned char *>(mul + a.n_max);  // serial: syndrome byte per check
@@ -132,10 +131,8 @@ void bp_wave_kernel(BPArgs a) {
                 }
                 const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-                for (int k = 0; k < kMaxVarDegree; ++k) {
-                    const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-                    ea[v][k] = ibase_addr + 4u * ((e & 7u) * (uint32_t)S + (e >> 3));
-                }
+                for (int k = 0; k < kMaxVarDegree; ++k)
+                    ea[v][k] = LY::edge_word(ibase_addr, (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu);
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
                 if (!a.prior_per_shot) mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
@@ -191,7 +188,8 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
             for (int c = 0; c < PC; ++c) {
                 const int j = c * 64 + lane;
-                const int src = csrcp[c];
+                int src = csrcp[c];
+                asm volatile("" : "+v"(src));  // derive the syndrome word address per shot (not kept live)
                 if (src != kJunkRow) {
                     rowv |= 1u << c;
                     uint32_t bit = 0;
@@ -219,6 +217,10 @@ void bp_wave_kernel(BPArgs a) {
                 const uint16_t *lc = pt->lev_chk + (size_t)l * Mmax;
                 const uint4 *lt = pt->ltab + (size_t)l * Mmax * 8;
                 while (true) {
+    #pragma unroll
+                    for (int v = 0; v < PV; ++v)
+    #pragma unroll
+                        for (int k = 0; k < kMaxVarDegree; ++k) asm volatile("" : "+v"(ea[v][k]));
                     // ---------------- posterior phase (r = 0 at iteration 0)
 #pragma unroll
                     for (int v = 0; v < PV; ++v) {
@@ -227,14 +229,14 @@ void bp_wave_kernel(BPArgs a) {
                             float Pv = 0.0f;
                             bool d = false;
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_post<1, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 2: var_post<2, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 3: var_post<3, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 4: var_post<4, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 5: var_post<5, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 6: var_post<6, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 7: var_post<7, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
-                            case 8: var_post<8, LY>(ea[v], deg, mu[v], dconst, Pv, d); break;
+                            case 1: var_post<1, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 2: var_post<2, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 3: var_post<3, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 4: var_post<4, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 5: var_post<5, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 6: var_post<6, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 7: var_post<7, LY>(ea[v], deg, mu[v], Pv, d); break;
+                            case 8: var_post<8, LY>(ea[v], deg, mu[v], Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
@@ -247,11 +249,8 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = c * 64 + lane;
-                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + LY::kDecMul * (uint32_t)j);
-                        uint32_t par = (sbits >> c) & 1u;
-#pragma unroll
-                        for (int k = 0; k < DC; ++k) par ^= drow[LY::kDecMul * k * S];
-                        unsat |= par & ((rowv >> c) & 1u);
+                        const uint64_t dw = *lds_ptr_u64(ibase_addr + LY::kDecOff + 8u * (uint32_t)j);
+                        unsat |= (row_parity(dw) ^ (sbits >> c)) & ((rowv >> c) & 1u);
                     }
                     const bool sat = __ballot(unsat != 0u) == 0ull;
                     if (!a.fixed_T) {
@@ -311,35 +310,41 @@ void bp_wave_kernel(BPArgs a) {
                         }
                     }
                     // ---------------- variable phase
+                    // the edge words are unpacked where they are used, not once per shot (which
+                    // would keep both halves of every word live in registers)
+    #pragma unroll
+                    for (int v = 0; v < PV; ++v)
+    #pragma unroll
+                        for (int k = 0; k < kMaxVarDegree; ++k) asm volatile("" : "+v"(ea[v][k]));
     #pragma unroll
                     for (int v = 0; v < PV; ++v) {
-                        if (v < vp) {
+                        if (v < vp && v * 64 + lane < n) {
                             const int deg = (int)(vinfo[v] >> 16);
                             float Pv = 0.0f;
                             bool d = false;
                             const bool prevd = (decb >> v) & 1u;
                             if (!kClearPerShot && it == 0) {
                                 switch (uniform_i32(dmaxp[v])) {
-                                case 1: var_first<1, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 2: var_first<2, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 3: var_first<3, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 4: var_first<4, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 5: var_first<5, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 6: var_first<6, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 7: var_first<7, LY>(ea[v], mu[v], dconst, Pv, d); break;
-                                case 8: var_first<8, LY>(ea[v], mu[v], dconst, Pv, d); break;
+                                case 1: var_first<1, LY>(ea[v], mu[v], Pv, d); break;
+                                case 2: var_first<2, LY>(ea[v], mu[v], Pv, d); break;
+                                case 3: var_first<3, LY>(ea[v], mu[v], Pv, d); break;
+                                case 4: var_first<4, LY>(ea[v], mu[v], Pv, d); break;
+                                case 5: var_first<5, LY>(ea[v], mu[v], Pv, d); break;
+                                case 6: var_first<6, LY>(ea[v], mu[v], Pv, d); break;
+                                case 7: var_first<7, LY>(ea[v], mu[v], Pv, d); break;
+                                case 8: var_first<8, LY>(ea[v], mu[v], Pv, d); break;
                                 default: Pv = mu[v]; d = Pv < 0.0f; break;
                                 }
                             } else {
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_rule<1, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 2: var_rule<2, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 3: var_rule<3, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 4: var_rule<4, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 5: var_rule<5, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 6: var_rule<6, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 7: var_rule<7, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
-                            case 8: var_rule<8, LY>(ea[v], deg, mu[v], prevd, dconst, Pv, d); break;
+                            case 1: var_rule<1, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 2: var_rule<2, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 3: var_rule<3, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 4: var_rule<4, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 5: var_rule<5, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 6: var_rule<6, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 7: var_rule<7, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 8: var_rule<8, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             }
@@ -366,14 +371,10 @@ void bp_wave_kernel(BPArgs a) {
                     for (int c = 0; c < PC; ++c) {
                         const int j = c * 64 + lane;
                         const lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
-                        const lds_u8 *drow = lds_ptr_u8(ibase_addr + LY::kDecOff + LY::kDecMul * (uint32_t)j);
-                        uint32_t par = (sbits >> c) & 1u;
     #pragma unroll
-                        for (int k = 0; k < DC; ++k) {
-                            qa[c][k] = row[k * S];
-                            par ^= drow[LY::kDecMul * k * S];
-                        }
-                        unsat |= par & ((rowv >> c) & 1u);
+                        for (int k = 0; k < DC; ++k) qa[c][k] = row[k * S];
+                        const uint64_t dw = *lds_ptr_u64(ibase_addr + LY::kDecOff + 8u * (uint32_t)j);
+                        unsat |= (row_parity(dw) ^ (sbits >> c)) & ((rowv >> c) & 1u);
                     }
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {

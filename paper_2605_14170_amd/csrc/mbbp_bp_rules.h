@@ -18,19 +18,39 @@ constexpr int kRuleNMS = 0, kRuleSPA = 1, kRuleWeighted = 2;
 template <int RULE>
 struct CheckRule;
 
+// XOR of N >= 2 words with three-input XORs (v_bitop3, truth table 0x96).
+template <int N>
+__device__ __forceinline__ uint32_t xor_all(const uint32_t (&x)[N]) {
+    uint32_t acc;
+    int k;
+    if constexpr (N >= 3) {
+        acc = __builtin_amdgcn_bitop3_b32(x[0], x[1], x[2], 0x96);
+        k = 3;
+    } else {
+        acc = x[0] ^ x[1];
+        k = 2;
+    }
+#pragma unroll
+    for (; k + 2 <= N; k += 2) acc = __builtin_amdgcn_bitop3_b32(acc, x[k], x[k + 1], 0x96);
+    if (k < N) acc ^= x[k];
+    return acc;
+}
+
 // Two smallest magnitudes of a row (m1 <= m2, equal on a tie) and the XOR of all
 // sign bits.
 template <int DC>
 __device__ __forceinline__ void row_min2(const float (&q)[DC], float &m1, float &m2, uint32_t &sx) {
     m1 = fminf(fabsf(q[0]), fabsf(q[1]));
     m2 = fmaxf(fabsf(q[0]), fabsf(q[1]));
-    sx = fbits(q[0]) ^ fbits(q[1]);
+    uint32_t b[DC];
+#pragma unroll
+    for (int k = 0; k < DC; ++k) b[k] = fbits(q[k]);
+    sx = xor_all<DC>(b);
 #pragma unroll
     for (int k = 2; k < DC; ++k) {
         const float a = fabsf(q[k]);
         m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
         m1 = fminf(m1, a);
-        sx ^= fbits(q[k]);
     }
 }
 
@@ -176,18 +196,19 @@ struct WeightedRule {
 };
 
 // LDS layout of one BP instance, 64 * PC row positions (Mpad), slot stride
-// S = Mpad + kSlotPad words.  Two forms: the wide one (8 slots, one 32-bit cell per
-// decision at a fixed offset from the message, so a message's address plus an
-// immediate reaches its decision) and, for large codes whose instances would
-// otherwise leave most of a CU idle for want of LDS, the compact one (DC slots, one
-// byte per decision at (message address >> 2) + dconst):
+// S = Mpad + kSlotPad words.  Two forms: the wide one (8 message slots) and, for
+// large codes whose instances would otherwise leave most of a CU idle for want of
+// LDS, the compact one (DC slots):
 //   messages  float [slots][S]  slot-major: edge (p, k) at k * S + p
-//   decisions [slots][S]        cells of kDecMul bytes
+//   decisions u8 [Mpad][8]      row-major: edge (p, k) at 8 * p + k, so a check lane
+//                               reads all of its row's decisions with one 8-byte load
 //   weighted rule only: c->v messages float [slots][S] (the message array then holds
 //                               the v->c messages only)
 //   syndrome words, output staging words, per-shot priors.
+// A variable lane keeps one word per edge: the message's byte address in the low
+// half and its decision byte's address in the high half (LDS addresses fit 16 bits).
 // Junk positions are unused by representation l; position Mmax (of the part) is the
-// sink of absent edges.  Every table entry is a byte address in LDS.
+// sink of absent edges.
 template <int PC, int RULE = kRuleNMS, int DC = 8>
 struct Layout {
     static constexpr bool kCompact = PC >= 9;
@@ -195,16 +216,23 @@ struct Layout {
     static constexpr int Mpad = 64 * PC;
     static constexpr int S = Mpad + kSlotPad;                                   // slot stride (words)
     static constexpr uint32_t kMsg = (4u * kSlots * S + 15u) & ~15u;            // bytes of a message array
-    static constexpr uint32_t kDecMul = kCompact ? 1u : 4u;                     // bytes per decision cell
-    static constexpr uint32_t kDec = (kDecMul * kSlots * S + 15u) & ~15u;       // bytes of the decisions
+    static constexpr uint32_t kDec = (8u * Mpad + 15u) & ~15u;                  // bytes of the decisions
     static constexpr uint32_t kDecOff = kMsg;                                   // decisions after the messages
     static constexpr uint32_t kROff = RULE == kRuleWeighted ? kMsg + kDec : 0u;  // where c->v messages live
     static constexpr uint32_t kTail = kMsg + kDec + (RULE == kRuleWeighted ? kMsg : 0u);  // syndrome words
-    // byte address of the decision cell of the edge whose message is at byte address ea
-    __device__ __forceinline__ static uint32_t dec(uint32_t ea, uint32_t dconst) {
-        return kCompact ? (ea >> 2) + dconst : ea + kDecOff;
+    // the two halves of a packed edge word
+    __device__ __forceinline__ static uint32_t msg(uint32_t ea) { return ea & 0xffffu; }
+    __device__ __forceinline__ static uint32_t dec(uint32_t ea) { return ea >> 16; }
+    // packed edge word of edge id e = position * 8 + slot
+    __device__ __forceinline__ static uint32_t edge_word(uint32_t ibase_addr, uint32_t e) {
+        const uint32_t m = ibase_addr + 4u * ((e & 7u) * (uint32_t)S + (e >> 3));
+        const uint32_t d = ibase_addr + kDecOff + 8u * (e >> 3) + (e & 7u);
+        return m | (d << 16);
     }
 };
+
+// Parity of a row's hard decisions (one byte, 0 or 1, per slot; unused slots 0).
+__device__ __forceinline__ uint32_t row_parity(uint64_t dw) { return (uint32_t)__popcll(dw) & 1u; }
 
 // Exclusion sums of a variable of degree <= D with incoming messages r (unused
 // slots hold 0): q_k = mu + sum_{k' != k} r_k' and P = mu + sum r, both
@@ -225,17 +253,17 @@ __device__ __forceinline__ float excl_sums(const float (&r)[D], float mu, float 
 
 // Variable rule (eq. (2) and the posterior of Section II-B) for a variable of
 // degree deg <= D (edges k >= deg point at the sink and read as 0): reads the c->v
-// messages at ea + ROFF, writes every q_k at ea and the hard decision at ea + DECOFF.
-// prev is the decision already stored in the cells: when no lane of the wave changed
-// its decision the cell stores are skipped (must be called by all 64 lanes).
+// messages at msg(ea) + ROFF, writes every q_k at msg(ea) and the hard decision at
+// dec(ea).  prev is the decision already stored in the cells: when no active lane
+// changed its decision the cell stores are skipped (called by every lane that holds
+// a variable of the pass).
 template <int D, typename LY>
-__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, uint32_t dconst, float &P,
-                                         bool &dec) {
+__device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, float &P, bool &dec) {
     constexpr uint32_t ROFF = LY::kROff;
     float r[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const float x = *lds_ptr_f32(ea[k] + ROFF);
+        const float x = *lds_ptr_f32(LY::msg(ea[k]) + ROFF);
         r[k] = k < deg ? x : 0.0f;
     }
     float q[D];
@@ -243,10 +271,10 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     dec = pre < 0.0f;
     P = pre;
 #pragma unroll
-    for (int k = 0; k < D; ++k) *lds_ptr_f32(ea[k]) = q[k];
+    for (int k = 0; k < D; ++k) *lds_ptr_f32(LY::msg(ea[k])) = q[k];
     if (__ballot(dec != prev) != 0ull) {
 #pragma unroll
-        for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k], dconst)) = (unsigned char)dec;
+        for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k])) = (unsigned char)dec;
     }
 }
 
@@ -254,30 +282,30 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
 // 0: q_k = P = mu (stored as-is; mu is canonical, never -0), and every decision cell
 // is written, so nothing left from an earlier shot is read later.
 template <int D, typename LY>
-__device__ __forceinline__ void var_first(const uint32_t *ea, float mu, uint32_t dconst, float &P, bool &dec) {
+__device__ __forceinline__ void var_first(const uint32_t *ea, float mu, float &P, bool &dec) {
     dec = mu < 0.0f;
     P = mu;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        *lds_ptr_f32(ea[k]) = mu;
-        *lds_ptr_u8(LY::dec(ea[k], dconst)) = (unsigned char)dec;
+        *lds_ptr_f32(LY::msg(ea[k])) = mu;
+        *lds_ptr_u8(LY::dec(ea[k])) = (unsigned char)dec;
     }
 }
 
 // Posterior only (serial schedule): P = mu + sum r in ascending check order and the
 // hard decision written to every edge's decision cell; messages are left alone.
 template <int D, typename LY>
-__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, uint32_t dconst, float &P, bool &dec) {
+__device__ __forceinline__ void var_post(const uint32_t *ea, int deg, float mu, float &P, bool &dec) {
     float pre = mu;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const float x = *lds_ptr_f32(ea[k]);
+        const float x = *lds_ptr_f32(LY::msg(ea[k]));
         pre += k < deg ? x : 0.0f;
     }
     dec = pre < 0.0f;
     P = pre;
 #pragma unroll
-    for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k], dconst)) = (unsigned char)dec;
+    for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k])) = (unsigned char)dec;
 }
 
 }  // namespace mbbp

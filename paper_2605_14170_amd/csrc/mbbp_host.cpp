@@ -536,7 +536,7 @@ int lds_slots(const mbbp_ctx *c, int part0, int nparts, int mpad) {
 }
 
 // LDS bytes of one BP instance (must match Layout in mbbp_bp_rules.h): messages
-// (DC slots of stride Mpad + kSlotPad words, 16-byte rounded), decision bytes, for
+// (slots of stride Mpad + kSlotPad words, 16-byte rounded), 8 decision bytes per row, for
 // the weighted rule the c->v messages, the syndrome words, the output staging words
 // and, for per-shot priors or the serial schedule, the shot's n priors.
 bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, int rule,
@@ -554,8 +554,7 @@ bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, 
     a.n_max = n;
     const int stride = mpad + mbbp::kSlotPad;  // slot stride of the LDS arrays (words)
     const int slots = lds_slots(c, part0, nparts, mpad);
-    const int cell = mpad >= 64 * kCompactPC ? 1 : 4;  // bytes per decision cell
-    const int msg = (4 * slots * stride + 15) & ~15, dec = (cell * slots * stride + 15) & ~15;
+    const int msg = (4 * slots * stride + 15) & ~15, dec = (8 * mpad + 15) & ~15;  // decisions: 8 bytes per row
     a.msg_bytes = msg;
     a.zero_bytes = msg + dec;
     // serial schedule: priors always staged (n floats) plus one syndrome byte per row
