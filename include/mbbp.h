@@ -84,6 +84,10 @@ typedef struct {
 } mbbp_bases;
 
 #define MBBP_FLAG_FIXED_T 1u  /* diagnostic: run exactly T iterations, no early stop */
+/* One BP instance per wavefront everywhere.  By default flooding min-sum with early
+ * stop and one prior vector runs two instances (two shots of a representation) per
+ * wavefront; results are identical either way (for comparison and testing). */
+#define MBBP_FLAG_ONE_PER_WAVE 2u
 
 typedef struct {
     int32_t rule;        /* mbbp_rule, default MBBP_NMS; MBBP_WEIGHTED needs MBBP_FLOODING */
@@ -189,7 +193,9 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
  * form: 0 = mbbp_decode / mbbp_decode_detail, 1 = mbbp_decode_batched / mbbp_run.
  * lanes_per_instance: 64 (one instance per wavefront; other values: MBBP_EUNSUPPORTED);
  * waves_per_block >= 1 (reduced automatically to fit 64 KiB of LDS);
- * chunk: shots per work item (64-lane kernel: decoded one after another by a wave);
+ * chunk: shots per work item, decoded one after another by a wave (default 8 for
+ *   form 0, 64 for form 1; the paired kernel, two instances per wavefront, serves
+ *   items of at most 128 shots, larger ones run one instance per wavefront);
  * blocks: persistent grid size (form 1; 0 = 4 per compute unit).
  * Every configuration gives bit-identical outputs.  MBBP_EUNSUPPORTED if the code
  * does not fit the register tables of that lane count. */

@@ -110,7 +110,7 @@ class Decoder:
                  schedule: int = FLOODING, rule: int = NMS, alpha: float = 0.875,
                  r_max: float = 65536.0, select: int = MIN_WEIGHT, max_batch: int = 1 << 20,
                  fixed_T: bool = False, extra_hx: Optional[np.ndarray] = None,
-                 extra_hz: Optional[np.ndarray] = None):
+                 extra_hz: Optional[np.ndarray] = None, one_per_wave: bool = False):
         L_ = _lib.lib()
         self.n = int(hx.shape[1])
         self.mx, self.mz = int(hx.shape[0]), int(hz.shape[0])
@@ -136,7 +136,8 @@ class Decoder:
         L_.mbbp_params_default(ctypes.byref(prm))
         prm.rule, prm.alpha, prm.r_max, prm.select = int(rule), float(alpha), float(r_max), int(select)
         prm.max_batch = int(max_batch)
-        prm.flags = _lib.MBBP_FLAG_FIXED_T if fixed_T else 0
+        prm.flags = (_lib.MBBP_FLAG_FIXED_T if fixed_T else 0) | \
+            (_lib.MBBP_FLAG_ONE_PER_WAVE if one_per_wave else 0)
         ctx = ctypes.c_void_p()
         _lib.check(L_.mbbp_create(ctypes.byref(spx.s), ctypes.byref(spz.s), ctypes.byref(bases), int(T),
                                   int(schedule), ctypes.byref(prm), ctypes.byref(ctx)), "mbbp_create")

@@ -16,6 +16,7 @@ MBBP_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTINROWSPACE", -3: "ENOMEM", -4: "EDEVICE",
                 -5: "EUNSUPPORTED", -6: "EABORTED"}
 MBBP_FLAG_FIXED_T = 1
+MBBP_FLAG_ONE_PER_WAVE = 2
 NUM_COUNTERS = 8
 
 

@@ -552,6 +552,7 @@ static hipError_t launch_sched(const BPArgs &a, const BPConfig &cfg, int rule, c
 
 hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s) {
     if ((schedule != 0 && schedule != 1) || cfg.lpi != 64) return hipErrorInvalidValue;
+    if (a.dual) return schedule == 0 && rule == kRuleNMS ? launch_bp_dual(a, cfg, s) : hipErrorInvalidValue;
     int pv, pc;
     passes_needed(a, pv, pc);
     PassPair pp;

@@ -1,0 +1,412 @@
+// Paired form of the flooding min-sum BP kernel (Section II-B, eqs. (1)-(2)): two
+// BP instances of one representation (two shots of a work item) per wavefront.
+//
+// With one instance per wavefront a code of n = 144 variables and up to 96 check
+// positions fills 3 variable passes and 2 check passes of 64 lanes, 75% and at most
+// 75% of them useful; every pass costs the same LDS instructions however few of its
+// lanes are live.  Pairing interleaves the two instances lane by lane: lane i works
+// for instance i & 1 on variable rank 32 * v + (i >> 1) and check position
+// 32 * c + (i >> 1), so 2n variables take ceil(2n / 64) passes and 2 * Mpad
+// positions 2 * Mpad / 64 passes (5 and 3 for the code above, instead of 6 and 4).
+//
+// Each instance keeps its own LDS region (messages, decisions, syndrome and staging
+// words), its own shot and iteration count.  When an instance halts (Section II-B:
+// syndrome satisfied, or T iterations) its outputs are written, its c->v messages
+// are reset to 0 and it takes the next shot of the work item at once, while the
+// other instance keeps iterating; an iteration with all c->v messages 0 computes
+// exactly what the first variable phase of a shot computes (q = P = mu).  Values are
+// those of the one-instance kernel bit for bit.  Used for normalized min-sum with
+// early stop and one prior vector; the other forms use one instance per wavefront.
+#include <hip/hip_runtime.h>
+
+#include "mbbp_bp_rules.h"
+#include "mbbp_device.h"
+#include "mbbp_wave.h"
+
+namespace mbbp {
+
+namespace {
+
+struct DualItem {
+    int part, l;
+    int64_t begin, end;
+};
+
+__device__ __forceinline__ DualItem dual_item(const BPArgs &a, int64_t item) {
+    const int64_t rank = item / a.n_chunks;
+    const int64_t ch = item - rank * a.n_chunks;
+    const int pl = a.item_order ? a.item_order[rank] : (int)rank;
+    DualItem p;
+    p.part = a.part0 + pl / a.L;
+    p.l = pl - (pl / a.L) * a.L;
+    p.begin = ch * a.chunk;
+    p.end = min(p.begin + (int64_t)a.chunk, a.shots);
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T pick2(const T (&v)[2], int part) { return part == 0 ? v[0] : v[1]; }
+
+constexpr uint64_t kLanes0 = 0x5555555555555555ull;  // lanes of instance 0
+
+}  // namespace
+
+// PV2 / PC2: variable / check passes of 64 lanes covering both instances; an
+// instance has 32 * PC2 check positions.  DC as in bp_wave_kernel; MAXD: largest
+// variable degree (edge words kept per variable); LLR: posteriors are written.
+template <int PV2, int PC2, int DC, int MAXD, bool LLR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void bp_dual_kernel(BPArgs a) {
+    using LY = LayoutM<32 * PC2, kRuleNMS, DC, false>;
+    constexpr int S = LY::S;
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const int comp = lane & 1;   // instance of this lane
+    const int half = lane >> 1;  // rank within the instance's pass
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int istride = a.dual_stride;  // bytes per instance region
+    unsigned char *wbase = smem + (size_t)wib * a.inst_bytes;
+    unsigned char *cbase = wbase + comp * istride;
+    const uint32_t cbase_addr = (uint32_t)(size_t)(lds_u8 *)cbase;
+    // instance tails: output staging words; after both regions, the syndrome words of
+    // every shot of the work item (staged once per item, so no shot waits on memory)
+    uint32_t *stage[2] = {reinterpret_cast<uint32_t *>(wbase + LY::kTail),
+                          reinterpret_cast<uint32_t *>(wbase + istride + LY::kTail)};
+    uint64_t *sbuf = reinterpret_cast<uint64_t *>(wbase + 2 * istride);
+
+    int64_t item;
+    if (a.persistent) {
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(a.queue, 1ull);
+        item = uniform_i64((long long)v);
+    } else {
+        item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+    }
+    const float alpha = a.alpha, rmax = a.rmax;
+    const int T = a.T;
+    int cur_key = -1;
+
+    uint32_t ea[PV2][MAXD];           // packed edge words (message | decision << 16)
+    uint32_t vinfo[PV2];              // variable id | degree << 16
+    int dmaxp[PV2];
+    uint32_t cwp[PC2];
+    float mu[PV2];
+    int32_t csrcp[PC2];
+    uint32_t rowv = 0;   // check pass c holds a real check of this lane's instance
+    uint32_t decb = 0;   // decisions of the last variable phase (as stored in the cells)
+    float Pl[LLR ? PV2 : 1];          // posteriors of the last variable phase (LLR only)
+
+    while (item < a.n_items) {
+        const DualItem ip = dual_item(a, item);
+        const DevPart *pt = a.dparts + ip.part;
+        const int n = pt->n, Mmax = pt->Mmax, W = pt->W, Ws = pt->Ws, L = pt->L;
+        const int l = ip.l;
+        const int key = ip.part * 256 + l;
+        if (key != cur_key) {
+            cur_key = key;
+            const uint4 *vo4 = reinterpret_cast<const uint4 *>(pt->voff) + (size_t)l * n;
+            const uint16_t *vid = pt->vid + (size_t)l * n;
+            const uint8_t *vdg = pt->vdeg + (size_t)l * n;
+            const float *pr0 = pick2(a.prior, ip.part);
+            const uint32_t sink = (uint32_t)Mmax * 8u;
+#pragma unroll
+            for (int v = 0; v < PV2; ++v) {
+                const int s1 = v * 32 + half;
+                const bool valid = s1 < n;
+                const uint32_t sk2 = sink | (sink << 16);
+                uint4 o = make_uint4(sk2, sk2, sk2, sk2);
+                int deg = 0;
+                uint32_t id = 0;
+                if (valid) {
+                    o = vo4[s1];
+                    deg = vdg[s1];
+                    id = vid[s1];
+                }
+                const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+                for (int k = 0; k < MAXD; ++k)
+                    ea[v][k] = LY::edge_word(cbase_addr, (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+                vinfo[v] = id | ((uint32_t)deg << 16);
+                dmaxp[v] = uniform_i32(wave_max_i32(deg));
+                mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
+                if constexpr (LLR) Pl[v] = 0.0f;
+            }
+            const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
+            rowv = 0;
+#pragma unroll
+            for (int c = 0; c < PC2; ++c) {
+                const int p = c * 32 + half;
+                csrcp[c] = p < Mmax ? csrc[p] : kJunkRow;
+                if (csrcp[c] != kJunkRow) rowv |= 1u << c;
+                if (DC == 8) cwp[c] = p < Mmax ? (uint32_t)pt->cw[(size_t)l * Mmax + p] : 8u;
+            }
+            // both regions from scratch: messages, decisions (and the decision bits) 0
+            uint4 *z = reinterpret_cast<uint4 *>(wbase);
+            const int nz = a.inst_bytes >> 4;
+            for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+            decb = 0;
+        }
+        const uint64_t *syn = pick2(a.syn, ip.part);
+        uint64_t *cand = pick2(a.cand, ip.part);
+        uint16_t *kstat = pick2(a.kstat, ip.part);
+        float *llr = pick2(a.llr, ip.part);
+        (void)llr;
+
+        // syndrome words of the item's shots (at most the chunk the host sized sbuf for)
+        {
+            const int nw = (int)(ip.end - ip.begin) * Ws;
+            for (int i = lane; i < nw; i += 64) sbuf[i] = syn[ip.begin * Ws + i];
+        }
+        // per-instance state (wave-uniform): current shot (-1: idle) and iteration
+        int64_t next = ip.begin;
+        int64_t shot[2] = {-1, -1};
+        int it[2] = {0, 0};
+        uint32_t fresh = 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            if (next < ip.end) { shot[c] = next++; fresh |= 1u << c; }
+        uint32_t sbits = 0;  // syndrome bit of this lane's check in each pass
+        wave_sync();
+
+        while (shot[0] >= 0 || shot[1] >= 0) {
+            // ---------------- a fresh shot (its syndrome words already staged): c->v messages 0
+            // (an idle instance kept iterating on its last shot), derive the check bits
+            if (fresh) {
+                if ((fresh >> comp) & 1u) {
+#pragma unroll
+                    for (int c = 0; c < PC2; ++c) {
+                        lds_f32 *row = lds_ptr_f32(cbase_addr + 4u * (uint32_t)(c * 32 + half));
+#pragma unroll
+                        for (int k = 0; k < DC; ++k) row[k * S] = 0.0f;
+                    }
+                }
+                wave_sync();
+                if ((fresh >> comp) & 1u) {
+                    sbits = 0;
+                    const uint64_t *sy = sbuf + (shot[comp] - ip.begin) * Ws;
+#pragma unroll
+                    for (int c = 0; c < PC2; ++c) {
+                        int src = csrcp[c];
+                        asm volatile("" : "+v"(src));
+                        if (src != kJunkRow) {
+                            uint32_t bit = 0;
+                            if (src >= 0) {
+                                bit = (uint32_t)(sy[src >> 6] >> (src & 63)) & 1u;
+                            } else {
+                                for (int t = pt->comb_ptr[-src - 1]; t < pt->comb_ptr[-src]; ++t) {
+                                    const int r = pt->comb_idx[t];
+                                    bit ^= (uint32_t)(sy[r >> 6] >> (r & 63)) & 1u;
+                                }
+                            }
+                            sbits |= bit << c;
+                        }
+                    }
+                }
+                fresh = 0;
+                wave_sync();
+            }
+            // ---------------- variable phase (both instances)
+#pragma unroll
+            for (int v = 0; v < PV2; ++v)
+#pragma unroll
+                for (int k = 0; k < MAXD; ++k) asm volatile("" : "+v"(ea[v][k]));
+#pragma unroll
+            for (int v = 0; v < PV2; ++v) {
+                if (v * 32 + half < n) {
+                    const int deg = (int)(vinfo[v] >> 16);
+                    float Pv = 0.0f;
+                    bool d = false;
+                    const bool prevd = (decb >> v) & 1u;
+                    switch (uniform_i32(dmaxp[v])) {
+                    case 1: var_rule<1, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 2: var_rule<2, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 3: var_rule<3, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 4: if constexpr (MAXD >= 4) var_rule<4, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 5: if constexpr (MAXD >= 5) var_rule<5, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 6: if constexpr (MAXD >= 6) var_rule<6, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 7: if constexpr (MAXD >= 7) var_rule<7, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 8: if constexpr (MAXD >= 8) var_rule<8, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    default: Pv = mu[v]; d = Pv < 0.0f; break;
+                    }
+                    decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
+                    if constexpr (LLR) Pl[v] = Pv;
+                }
+            }
+            wave_sync();
+            // ---------------- check phase: syndrome test and c->v messages
+            uint32_t unsat = 0;
+            float qa[PC2][DC];
+#pragma unroll
+            for (int c = 0; c < PC2; ++c) {
+                const int p = c * 32 + half;
+                const lds_f32 *row = lds_ptr_f32(cbase_addr + 4u * (uint32_t)p);
+#pragma unroll
+                for (int k = 0; k < DC; ++k) qa[c][k] = row[k * S];
+                const uint64_t dw = *lds_ptr_u64(cbase_addr + LY::kDecOff + 8u * (uint32_t)p);
+                unsat |= (row_parity(dw) ^ (sbits >> c)) & ((rowv >> c) & 1u);
+            }
+#pragma unroll
+            for (int c = 0; c < PC2; ++c) {
+                const int p = c * 32 + half;
+                lds_f32 *row = lds_ptr_f32(cbase_addr + 4u * (uint32_t)p);
+                float (&q)[DC] = qa[c];
+                if constexpr (DC == 8) {
+                    const int w = (int)cwp[c];
+#pragma unroll
+                    for (int k = 2; k < DC; ++k)
+                        if (k >= w) q[k] = 3.402823466e38f;
+                }
+                CheckRule<kRuleNMS>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
+#pragma unroll
+                for (int k = 0; k < DC; ++k) row[k * S] = q[k];
+            }
+            // ---------------- halting of each instance (Section II-B)
+            const uint64_t ub = __ballot(unsat != 0u);
+            uint32_t done = 0, sat = 0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const bool s_c = (ub & (kLanes0 << c)) == 0ull;
+                sat |= (uint32_t)s_c << c;
+                if (shot[c] >= 0 && (s_c || it[c] == T)) done |= 1u << c;
+            }
+            if (done) {
+                wave_sync();
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (!((done >> c) & 1u)) continue;
+                    const bool conv = (sat >> c) & 1u;
+                    const int K = conv ? it[c] : T;
+                    const size_t inst = (size_t)shot[c] * L + l;
+                    if constexpr (LLR) {
+                        if (comp == c) {
+#pragma unroll
+                            for (int v = 0; v < PV2; ++v)
+                                if (v * 32 + half < n) llr[inst * n + (vinfo[v] & 0xffffu)] = Pl[v];
+                        }
+                    }
+                    // bit-packed hard decisions via the instance's staging words
+                    if (lane < 2 * W) stage[c][lane] = 0u;
+                    wave_sync();
+                    if (comp == c) {
+#pragma unroll
+                        for (int v = 0; v < PV2; ++v)
+                            if (v * 32 + half < n && ((decb >> v) & 1u)) {
+                                const uint32_t id = vinfo[v] & 0xffffu;
+                                atomicOr(&stage[c][id >> 5], 1u << (id & 31));
+                            }
+                    }
+                    wave_sync();
+                    if (lane < W) cand[inst * W + lane] = reinterpret_cast<const uint64_t *>(stage[c])[lane];
+                    if (lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
+                    it[c] = 0;
+                    if (next < ip.end) {
+                        shot[c] = next++;
+                        fresh |= 1u << c;
+                    } else {
+                        shot[c] = -1;
+                    }
+                }
+                wave_sync();
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                if (!((done >> c) & 1u)) ++it[c];
+            wave_sync();
+        }
+
+        if (a.persistent) {
+            unsigned long long v = 0;
+            if (lane == 0) v = atomicAdd(a.queue, 1ull);
+            item = uniform_i64((long long)v);
+        } else {
+            item = a.n_items;
+        }
+    }
+}
+
+namespace {
+
+struct DualPair {
+    int pv, pc;
+};
+// (variable passes, check passes) of the paired kernels, both instances together
+const DualPair kDualPairs[] = {{1, 1}, {2, 1}, {2, 2}, {3, 2}, {3, 3}, {4, 3}, {5, 3}, {5, 4}};
+constexpr int kDualMaxChunk = 128;         // shots of a work item (syndromes staged in LDS)
+constexpr int kDualMaxSynBytes = 4096;     // LDS for those syndrome words
+
+bool dual_pick(const BPArgs &a, DualPair &out) {
+    int pv = 1, pc = 1;
+    for (int p = a.part0; p < a.part0 + a.nparts; ++p) {
+        pv = max(pv, (2 * a.part[p].n + 63) / 64);
+        pc = max(pc, (a.part[p].Mmax + 1 + 31) / 32);  // positions of an instance incl. the sink
+    }
+    for (const DualPair &d : kDualPairs)
+        if (d.pv >= pv && d.pc >= pc) { out = d; return true; }
+    return false;
+}
+
+template <int PV2, int PC2, int DC, int MAXD, bool LLR>
+hipError_t launch_dual_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
+    const int wpb = cfg.waves_per_block;
+    const size_t lds = (size_t)wpb * a.inst_bytes;
+    const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
+    hipLaunchKernelGGL((bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
+                       a);
+    return hipGetLastError();
+}
+
+template <int PV2, int PC2, int DC>
+hipError_t launch_dual_dc(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
+    int maxd = 0;
+    bool llr = false;
+    for (int p = a.part0; p < a.part0 + a.nparts; ++p) {
+        maxd = max(maxd, a.part[p].max_deg);
+        llr = llr || a.llr[p] != nullptr;
+    }
+    if (maxd <= 6)
+        return llr ? launch_dual_t<PV2, PC2, DC, 6, true>(a, cfg, s) : launch_dual_t<PV2, PC2, DC, 6, false>(a, cfg, s);
+    return llr ? launch_dual_t<PV2, PC2, DC, 8, true>(a, cfg, s) : launch_dual_t<PV2, PC2, DC, 8, false>(a, cfg, s);
+}
+
+template <int PV2, int PC2>
+hipError_t launch_dual_pair(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
+    bool u6 = true;
+    for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
+    return u6 ? launch_dual_dc<PV2, PC2, 6>(a, cfg, s) : launch_dual_dc<PV2, PC2, 8>(a, cfg, s);
+}
+
+}  // namespace
+
+bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, int &stride) {
+    if (schedule != 0 || rule != kRuleNMS || a.fixed_T || a.prior_per_shot) return false;
+    if (a.chunk > kDualMaxChunk || a.chunk * a.ws_max * 8 > kDualMaxSynBytes) return false;
+    DualPair d;
+    if (!dual_pick(a, d)) return false;
+    const int mpad = 32 * d.pc;
+    const int msg = (4 * 8 * (mpad + kSlotPad) + 15) & ~15;  // LayoutM<mpad, NMS, DC, false>
+    const int dec = (8 * mpad + 15) & ~15;
+    const int bytes = msg + dec + a.w_max * 8;
+    // instance regions 64 bytes off a multiple of 128: the two instances' copies of
+    // one row lie 16 banks apart, so interleaved lanes never share a bank
+    stride = ((bytes + 127) & ~127) + 64;
+    inst_bytes = 2 * stride + ((a.chunk * a.ws_max * 8 + 15) & ~15);
+    return true;
+}
+
+hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
+    DualPair d;
+    if (!dual_pick(a, d)) return hipErrorInvalidValue;
+    switch (d.pv * 16 + d.pc) {
+    case 1 * 16 + 1: return launch_dual_pair<1, 1>(a, cfg, s);
+    case 2 * 16 + 1: return launch_dual_pair<2, 1>(a, cfg, s);
+    case 2 * 16 + 2: return launch_dual_pair<2, 2>(a, cfg, s);
+    case 3 * 16 + 2: return launch_dual_pair<3, 2>(a, cfg, s);
+    case 3 * 16 + 3: return launch_dual_pair<3, 3>(a, cfg, s);
+    case 4 * 16 + 3: return launch_dual_pair<4, 3>(a, cfg, s);
+    case 5 * 16 + 3: return launch_dual_pair<5, 3>(a, cfg, s);
+    case 5 * 16 + 4: return launch_dual_pair<5, 4>(a, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mbbp

@@ -195,7 +195,7 @@ struct WeightedRule {
     }
 };
 
-// LDS layout of one BP instance, 64 * PC row positions (Mpad), slot stride
+// LDS layout of one BP instance, Mpad row positions, slot stride
 // S = Mpad + kSlotPad words.  Two forms: the wide one (8 message slots) and, for
 // large codes whose instances would otherwise leave most of a CU idle for want of
 // LDS, the compact one (DC slots):
@@ -209,11 +209,11 @@ struct WeightedRule {
 // half and its decision byte's address in the high half (LDS addresses fit 16 bits).
 // Junk positions are unused by representation l; position Mmax (of the part) is the
 // sink of absent edges.
-template <int PC, int RULE = kRuleNMS, int DC = 8>
-struct Layout {
-    static constexpr bool kCompact = PC >= 9;
+template <int MPAD, int RULE, int DC, bool COMPACT>
+struct LayoutM {
+    static constexpr bool kCompact = COMPACT;
     static constexpr int kSlots = kCompact ? DC : 8;
-    static constexpr int Mpad = 64 * PC;
+    static constexpr int Mpad = MPAD;
     static constexpr int S = Mpad + kSlotPad;                                   // slot stride (words)
     static constexpr uint32_t kMsg = (4u * kSlots * S + 15u) & ~15u;            // bytes of a message array
     static constexpr uint32_t kDec = (8u * Mpad + 15u) & ~15u;                  // bytes of the decisions
@@ -230,6 +230,9 @@ struct Layout {
         return m | (d << 16);
     }
 };
+// one instance per wavefront: 64 * PC positions
+template <int PC, int RULE = kRuleNMS, int DC = 8>
+struct Layout : LayoutM<64 * PC, RULE, DC, (PC >= 9)> {};
 
 // Parity of a row's hard decisions (one byte, 0 or 1, per slot; unused slots 0).
 __device__ __forceinline__ uint32_t row_parity(uint64_t dw) { return (uint32_t)__popcll(dw) & 1u; }

@@ -29,6 +29,7 @@ struct DevPart {
     int W, Ws;          // 64-bit words of n bits / of m bits
     int Mmax;           // positions per representation (the sink is position Mmax)
     int uniform_dc;     // 6 if every row of every representation has weight 6, else 0
+    int max_deg;        // largest variable degree over the representations
     const int32_t *M;   // [L] checks of each representation
     const int32_t *E;   // [L] edges of each representation
     const uint16_t *voff;   // [L][n][8] edge ids of the variable in slot s, ascending check order
@@ -79,7 +80,9 @@ struct BPArgs {
     int n_pl;                // number of (part, l) pairs
     int64_t n_chunks;        // chunks per (part, l)
     unsigned long long *queue;
-    int inst_bytes;          // LDS bytes per instance
+    int dual;                // two instances per wavefront (bp_dual_kernel)
+    int dual_stride;         // bytes of one instance's LDS region in the paired kernel
+    int inst_bytes;          // LDS bytes per instance (per wavefront with dual: both instances)
     int msg_bytes;           // message rows of an instance: (Mmax + 1) * 8 floats
     int zero_bytes;          // message rows + decision rows (cleared at every fill), multiple of 16
     int ws_max, w_max;       // syndrome words / candidate words of the launch's parts
@@ -198,6 +201,10 @@ const void *run_prep_kernel_ptr();
 int bp_max_passes(int lpi);  // register slots available per lane for this lpi
 // Rows per instance (Mpad = 64 * check passes) of the kernel a launch would use; false if none fits.
 bool bp_layout(const BPArgs &a, int &mpad);
+// Paired form (two instances per wavefront): whether it serves this launch and, if
+// so, the LDS bytes per wavefront.
+bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, int &stride);
+hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s);
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();
 

@@ -289,9 +289,10 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
         P.M[l] = (int)reps[l].size();
         P.Mmax = std::max(P.Mmax, P.M[l]);
     }
-    // LDS row positions: the largest representation plus the sink, rounded up to whole
-    // 64-lane passes; position Mmax is the sink, the others are free for the layout
-    P.Mmax = 64 * ((P.Mmax + 1 + 63) / 64) - 1;
+    // LDS row positions: the largest representation plus the sink, rounded up to a
+    // multiple of 32 (half a 64-lane pass, so two instances fill whole passes in the
+    // paired kernel); position Mmax is the sink, the others are free for the layout
+    P.Mmax = 32 * ((P.Mmax + 1 + 31) / 32) - 1;
     if ((int64_t)(P.Mmax + 1) * 8 > 65535)
         return fail(MBBP_EUNSUPPORTED, std::string(name) + ": too many checks in a representation");
     bool all6 = true;
@@ -485,6 +486,8 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
     D.Ws = (P.m + 63) / 64;
     D.Mmax = P.Mmax;
     D.uniform_dc = P.uniform_dc;
+    D.max_deg = 0;
+    for (uint8_t d : P.vdeg) D.max_deg = std::max(D.max_deg, (int)d);
     mbbp_status st;
     if ((st = c->put(D.M, P.M)) != MBBP_OK) return st;
     if ((st = c->put(D.E, P.E)) != MBBP_OK) return st;
@@ -641,6 +644,14 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     a.queue = c->w_queue;
     if (!inst_layout(c, part0, nparts, pps != 0, c->schedule, rule, a))
         return fail(MBBP_EUNSUPPORTED, "code too large for the BP kernel's register tables");
+    // two instances per wavefront where the paired kernel serves the launch
+    int dual_bytes = 0, dual_stride = 0;
+    if (!(c->params.flags & MBBP_FLAG_ONE_PER_WAVE) &&
+        mbbp::bp_dual_layout(a, c->schedule, rule, dual_bytes, dual_stride)) {
+        a.dual = 1;
+        a.inst_bytes = dual_bytes;
+        a.dual_stride = dual_stride;
+    }
     mbbp::BPConfig run = cfg;
     if (persistent) {
         run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
@@ -862,7 +873,7 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
         if (!mbbp::bp_supported(lpi, need, c->dp[0].uniform_dc, prm.rule, schedule))
             return fail(MBBP_EUNSUPPORTED, "code too large for the register tables");
         c->plain_cfg = mbbp::BPConfig{lpi, 4, 8, 0};
-        c->batched_cfg = mbbp::BPConfig{lpi, 4, 16, c->cu_count * 4};
+        c->batched_cfg = mbbp::BPConfig{lpi, 4, 64, c->cu_count * 4};
         // workspace
         const int64_t B = prm.max_batch;
         for (int p = 0; p < 2; ++p) {
@@ -1191,7 +1202,7 @@ mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, 
     const int cu = ctx->cu_count;
     if (form == 1) {
         for (int wpb : {2, 4})
-            for (int chunk : {4, 16, 64})
+            for (int chunk : {4, 16, 64, 128})
                 for (int bpc : {2, 4, 8}) cands.push_back({64, wpb, chunk, cu * bpc});
     } else {
         for (int wpb : {1, 2, 4})

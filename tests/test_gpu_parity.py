@@ -519,3 +519,36 @@ def test_nms_large_codes_bit_exact(pk, factory, L, T, p, shots):
         np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
         say(f"  part {part}: mean K {ref.K.mean():.2f}")
     dec.close()
+
+
+@pytest.mark.parametrize("key,p,shots", [("bb144_L16_T50", 0.08, 2001), ("bb72_L4_T20", 0.06, 3001)])
+def test_paired_instances_equal_one_per_wave(pk, key, p, shots):
+    """Two instances per wavefront (default for flooding min-sum) and one instance per
+    wavefront give the same bits: per-representation decisions, iteration counts,
+    convergence flags and posteriors, in the plain and the persistent form, with work
+    items of an odd number of shots (one instance of a wave idles at the end)."""
+    wl = WORKLOADS[key]
+    code = wl.code()
+    decs = [make_decoder(pk, code, wl, max_batch=shots, one_per_wave=one)[0] for one in (False, True)]
+    ex, ez, sx, sz = decs[0].sample(5, p, 7, shots)
+    prior = torch.full((code.n,), f32(oracle.prior_llr(p)), dtype=torch.float32, device="cuda")
+    say(f"paired vs one per wave {key} p={p} shots={shots}")
+    for part, syn in ((0, sx), (1, sz)):
+        got = []
+        for d in decs:
+            cand, kstat, llr = d.decode_detail(part, syn, prior, want_llr=True)
+            torch.cuda.synchronize()
+            got.append((words(cand), kstat.cpu().numpy(), llr.cpu().numpy().view(np.uint32)))
+        for a, b, what in zip(got[0], got[1], ("decisions", "iterations", "posterior bits")):
+            np.testing.assert_array_equal(a, b, err_msg=f"part {part} {what}")
+    for chunk in (1, 7, 64):
+        outs = []
+        for d in decs:
+            d.set_config(1, 64, 4, chunk, 64)
+            outs.append(d.decode_batched(sx, sz, prior, prior))
+        torch.cuda.synchronize()
+        for k in outs[0]:
+            np.testing.assert_array_equal(outs[0][k].cpu().numpy(), outs[1][k].cpu().numpy(),
+                                          err_msg=f"chunk {chunk} {k}")
+    for d in decs:
+        d.close()
