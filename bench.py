@@ -64,7 +64,7 @@ def parse():
 
 
 # sources of the BP kernel; the recorded HBM traffic holds only for these as profiled
-KERNEL_SOURCES = ("mbbp_bp.hip", "mbbp_bp_rules.h", "mbbp_device.h", "mbbp_wave.h")
+KERNEL_SOURCES = ("mbbp_bp.hip", "mbbp_bp_dual.hip", "mbbp_bp_rules.h", "mbbp_device.h", "mbbp_wave.h")
 
 
 def recorded_traffic(workload, shots_per_launch):
@@ -72,7 +72,7 @@ def recorded_traffic(workload, shots_per_launch):
     summary, or None when that summary was taken on another BP kernel source or
     another launch size."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"bp_wave_kernel_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"bp_kernel_{workload}.md")
     csrc = os.path.join(ROOT, "paper_2605_14170_amd", "csrc")
     if not os.path.exists(path):
         return None
