@@ -437,7 +437,8 @@ void bp_wave_kernel(BPArgs a) {
                 }
             }
             wave_sync();
-            const size_t inst = (size_t)shot * L + l;
+            // representation-major: a work item's records are contiguous (whole-line writes)
+            const size_t inst = a.cand_rm ? (size_t)l * a.shots + shot : (size_t)shot * L + l;
             if (lane < W) cand[inst * W + lane] = reinterpret_cast<const uint64_t *>(stage)[lane];
             if (lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
             wave_sync();

@@ -296,8 +296,10 @@ void bp_dual_kernel(BPArgs a) {
                             }
                     }
                     wave_sync();
-                    if (lane < W) cand[inst * W + lane] = reinterpret_cast<const uint64_t *>(stage[c])[lane];
-                    if (lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
+                    // representation-major: a work item's records are contiguous
+                    const size_t oi = a.cand_rm ? (size_t)l * a.shots + shot[c] : inst;
+                    if (lane < W) cand[oi * W + lane] = reinterpret_cast<const uint64_t *>(stage[c])[lane];
+                    if (lane == 0) kstat[oi] = (uint16_t)(K | (conv ? 0x8000 : 0));
                     it[c] = 0;
                     if (next < ip.end) {
                         shot[c] = next++;

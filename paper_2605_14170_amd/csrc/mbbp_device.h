@@ -69,8 +69,9 @@ struct BPArgs {
     const uint64_t *syn[2];  // [shots][Ws]
     const float *prior[2];   // [n] or [shots][n]
     int prior_per_shot;
-    uint64_t *cand[2];       // [shots][L][W]
-    uint16_t *kstat[2];      // [shots][L]
+    uint64_t *cand[2];       // [shots][L][W], or [L][shots][W] with cand_rm
+    uint16_t *kstat[2];      // [shots][L], or [L][shots] with cand_rm
+    int cand_rm;             // candidates and iteration words representation-major
     float *llr[2];           // [shots][L][n] or null
     // work items
     int persistent;          // 0: item = global wave id, 1: atomic queue
@@ -133,8 +134,8 @@ struct SelectArgs {
     int rule;                // 0 least weight, 1 FWS
     int group;               // lanes per (part, shot); set by launch_select
     int64_t shots;
-    const uint64_t *cand[2];
-    const uint16_t *kstat[2];
+    const uint64_t *cand[2];     // [L][shots][W] (representation-major, as the BP kernels write them)
+    const uint16_t *kstat[2];    // [L][shots]
     uint64_t *corr[2];
     uint64_t *conv[2];
     int16_t *basis[2];

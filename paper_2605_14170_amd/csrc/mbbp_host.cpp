@@ -601,7 +601,8 @@ struct WeightedCall {
 
 mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint64_t *const syn[2],
                    const float *const prior[2], int pps, uint64_t *const cand[2], uint16_t *const kstat[2],
-                   float *const llr[2], bool persistent, hipStream_t s, const WeightedCall *wc = nullptr) {
+                   float *const llr[2], bool persistent, hipStream_t s, const WeightedCall *wc = nullptr,
+                   bool rep_major = true) {
     const int rule = wc ? (int)MBBP_WEIGHTED : c->params.rule;
     if (rule == MBBP_WEIGHTED && !wc && (!c->walpha || !c->wbeta))
         return fail(MBBP_EINVAL, "weighted rule: no weights set (mbbp_set_weights)");
@@ -624,6 +625,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         a.n_ck = wc ? wc->n_ck : 0;
     }
     a.shots = shots;
+    a.cand_rm = rep_major ? 1 : 0;
     a.prior_per_shot = pps;
     for (int p = 0; p < 2; ++p) {
         a.syn[p] = syn[p];
@@ -935,7 +937,7 @@ mbbp_status mbbp_decode_detail(mbbp_ctx *ctx, int32_t part, int64_t shots, const
     uint16_t *ks[2] = {kstat, kstat};
     float *ll[2] = {llr, llr};
     return run_bp(ctx, part, 1, shots, sy, pr, prior_per_shot ? 1 : 0, cd, ks, ll, false,
-                  static_cast<hipStream_t>(hip_stream));
+                  static_cast<hipStream_t>(hip_stream), nullptr, false);
 }
 
 static mbbp_status decode_common(mbbp_ctx *ctx, int64_t shots, const uint64_t *syn_x, const uint64_t *syn_z,

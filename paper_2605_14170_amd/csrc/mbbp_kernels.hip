@@ -111,8 +111,9 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(SampleArgs a) {
 // ----------------------------------------------------------------------------- select
 
 // A group of G lanes (G = the smallest power of two >= L) per (part, shot): lane
-// l of the group reads representation l's iteration word and candidate, so the
-// loads of a group cover the shot's contiguous candidate block together.  Items
+// l of the group reads representation l's iteration word and candidate; the
+// groups of a wave take consecutive shots, so each representation's loads of a
+// wave are contiguous (the records are representation-major).  Items
 // are (part, shot) pairs, part-major; each wave walks them in grid-stride rounds
 // (the round count is wave-uniform, so every group of a wave takes part in the
 // shuffles) and the counters are reduced per block before one atomic each.
@@ -135,16 +136,18 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
         const DevPart &pt = a.part[part];
         const int L = pt.L, W = pt.W;
         const bool mine = live && lg < L;
-        const uint64_t *cand = a.cand[part] + (size_t)shot * L * W;
+        // candidates and iteration words are representation-major: [L][shots][W], [L][shots]
+        const uint64_t *cand = a.cand[part] + (size_t)shot * W;
+        const size_t rstride = (size_t)a.shots * W;
         uint64_t words[WM];
         int st = 0, w = 0;
 #pragma unroll
         for (int i = 0; i < WM; ++i) words[i] = 0;
         if (mine) {
-            st = a.kstat[part][(size_t)shot * L + lg];
+            st = a.kstat[part][(size_t)lg * a.shots + shot];
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
-                if (i < W) words[i] = cand[(size_t)lg * W + i];
+                if (i < W) words[i] = cand[(size_t)lg * rstride + i];
                 w += __popcll(words[i]);
             }
             const int K = st & 0x7fff;
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
                 a.basis[part][shot] = (int16_t)best;
             }
             uint64_t *co = a.corr[part] + (size_t)shot * W;
-            for (int i = lg; i < W; i += G) co[i] = best >= 0 ? cand[(size_t)best * W + i] : 0ull;
+            for (int i = lg; i < W; i += G) co[i] = best >= 0 ? cand[(size_t)best * rstride + i] : 0ull;
         }
     }
     if (a.counters) {
