@@ -65,14 +65,14 @@ void bp_dual_kernel(BPArgs a) {
     const int half = lane >> 1;  // rank within the instance's pass
     extern __shared__ __align__(16) unsigned char smem[];
     const int istride = a.dual_stride;  // bytes per instance region
-    unsigned char *wbase = smem + (size_t)wib * a.inst_bytes;
-    unsigned char *cbase = wbase + comp * istride;
-    const uint32_t cbase_addr = (uint32_t)(size_t)(lds_u8 *)cbase;
+    // 32-bit LDS byte addresses; the wave's own ones are wave-uniform (scalar registers)
+    const uint32_t wbase_addr = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)(wib * a.inst_bytes)));
+    const uint32_t cbase_addr = wbase_addr + (uint32_t)(comp * istride);
     // instance tails: output staging words; after both regions, the syndrome words of
     // every shot of the work item (staged once per item, so no shot waits on memory)
-    uint32_t *stage[2] = {reinterpret_cast<uint32_t *>(wbase + LY::kTail),
-                          reinterpret_cast<uint32_t *>(wbase + istride + LY::kTail)};
-    uint64_t *sbuf = reinterpret_cast<uint64_t *>(wbase + 2 * istride);
+    const uint32_t stage_addr[2] = {wbase_addr + LY::kTail, wbase_addr + (uint32_t)istride + LY::kTail};
+    const uint32_t sbuf_addr = wbase_addr + 2u * (uint32_t)istride;
 
     int64_t item;
     if (a.persistent) {
@@ -141,9 +141,8 @@ void bp_dual_kernel(BPArgs a) {
                 if (DC == 8) cwp[c] = p < Mmax ? (uint32_t)pt->cw[(size_t)l * Mmax + p] : 8u;
             }
             // both regions from scratch: messages, decisions (and the decision bits) 0
-            uint4 *z = reinterpret_cast<uint4 *>(wbase);
-            const int nz = a.inst_bytes >> 4;
-            for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+            const int nz = a.inst_bytes >> 2;
+            for (int i = lane; i < nz; i += 64) lds_ptr_u32(wbase_addr)[i] = 0u;
             decb = 0;
         }
         const uint64_t *syn = pick2(a.syn, ip.part);
@@ -155,7 +154,7 @@ void bp_dual_kernel(BPArgs a) {
         // syndrome words of the item's shots (at most the chunk the host sized sbuf for)
         {
             const int nw = (int)(ip.end - ip.begin) * Ws;
-            for (int i = lane; i < nw; i += 64) sbuf[i] = syn[ip.begin * Ws + i];
+            for (int i = lane; i < nw; i += 64) lds_ptr_u64(sbuf_addr)[i] = syn[ip.begin * Ws + i];
         }
         // per-instance state (wave-uniform): current shot (-1: idle) and iteration
         int64_t next = ip.begin;
@@ -183,7 +182,7 @@ void bp_dual_kernel(BPArgs a) {
                 wave_sync();
                 if ((fresh >> comp) & 1u) {
                     sbits = 0;
-                    const uint64_t *sy = sbuf + (shot[comp] - ip.begin) * Ws;
+                    const lds_u64 *sy = lds_ptr_u64(sbuf_addr) + (shot[comp] - ip.begin) * Ws;
 #pragma unroll
                     for (int c = 0; c < PC2; ++c) {
                         int src = csrcp[c];
@@ -271,6 +270,14 @@ void bp_dual_kernel(BPArgs a) {
             }
             if (done) {
                 wave_sync();
+                // the output path recomputes what it derives from the variable ids (hoisting
+                // those per-shot values out of the loop would keep them live, spilled, all along)
+                uint32_t vid[PV2];
+#pragma unroll
+                for (int v = 0; v < PV2; ++v) {
+                    vid[v] = vinfo[v];
+                    asm volatile("" : "+v"(vid[v]));
+                }
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     if (!((done >> c) & 1u)) continue;
@@ -281,24 +288,24 @@ void bp_dual_kernel(BPArgs a) {
                         if (comp == c) {
 #pragma unroll
                             for (int v = 0; v < PV2; ++v)
-                                if (v * 32 + half < n) llr[inst * n + (vinfo[v] & 0xffffu)] = Pl[v];
+                                if (v * 32 + half < n) llr[inst * n + (vid[v] & 0xffffu)] = Pl[v];
                         }
                     }
                     // bit-packed hard decisions via the instance's staging words
-                    if (lane < 2 * W) stage[c][lane] = 0u;
+                    if (lane < 2 * W) lds_ptr_u32(stage_addr[c])[lane] = 0u;
                     wave_sync();
                     if (comp == c) {
 #pragma unroll
                         for (int v = 0; v < PV2; ++v)
                             if (v * 32 + half < n && ((decb >> v) & 1u)) {
-                                const uint32_t id = vinfo[v] & 0xffffu;
-                                atomicOr(&stage[c][id >> 5], 1u << (id & 31));
+                                const uint32_t id = vid[v] & 0xffffu;
+                                atomicOr((uint32_t *)(lds_ptr_u32(stage_addr[c]) + (id >> 5)), 1u << (id & 31));
                             }
                     }
                     wave_sync();
                     // representation-major: a work item's records are contiguous
                     const size_t oi = a.cand_rm ? (size_t)l * a.shots + shot[c] : inst;
-                    if (lane < W) cand[oi * W + lane] = reinterpret_cast<const uint64_t *>(stage[c])[lane];
+                    if (lane < W) cand[oi * W + lane] = lds_ptr_u64(stage_addr[c])[lane];
                     if (lane == 0) kstat[oi] = (uint16_t)(K | (conv ? 0x8000 : 0));
                     it[c] = 0;
                     if (next < ip.end) {
