@@ -59,7 +59,7 @@ __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 
 // over the conflict-free levels of the checks in which every check computes its
 // incoming messages from the latest check messages.
 template <int PV, int PC, int DC, int RULE, int SCHED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : (PV <= 5 ? 3 : 1))))
 void bp_wave_kernel(BPArgs a) {
     using LY = Layout<PC, RULE, DC>;
     static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
