@@ -67,12 +67,14 @@ void bp_wave_kernel(BPArgs a) {
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned char *ibase = smem + (size_t)wib * a.inst_bytes;
-    const uint32_t ibase_addr = (uint32_t)(size_t)(lds_u8 *)ibase;
-    uint64_t *synl = reinterpret_cast<uint64_t *>(ibase + LY::kTail);
-    uint32_t *stage = reinterpret_cast<uint32_t *>(synl + a.ws_max);
-    float *mul = reinterpret_cast<float *>(stage + 2 * a.w_max);
-    unsigned char *sbl = reinterpret_cast<unsigned char *>(mul + a.n_max);  // serial: syndrome byte per check
+    // 32-bit LDS byte addresses of this wave's instance (wave-uniform: scalar registers)
+    const uint32_t ibase_addr = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)(wib * a.inst_bytes)));
+    lds_u64 *synl = lds_ptr_u64(ibase_addr + LY::kTail);                           // syndrome words
+    lds_u32 *stage = lds_ptr_u32(ibase_addr + LY::kTail + 8u * (uint32_t)a.ws_max);  // output staging
+    lds_f32 *mul = lds_ptr_f32(ibase_addr + LY::kTail + 8u * (uint32_t)(a.ws_max + a.w_max));  // priors
+    lds_u8 *sbl = lds_ptr_u8(ibase_addr + LY::kTail + 8u * (uint32_t)(a.ws_max + a.w_max) +
+                             4u * (uint32_t)a.n_max);  // serial: syndrome byte per check
     constexpr bool kMuLds = SCHED == 1;  // the serial sweep reads priors from LDS
 
     int64_t item;
@@ -165,9 +167,8 @@ void bp_wave_kernel(BPArgs a) {
             // ---------------- fill: clear messages and decisions, stage syndrome (and priors)
             {
                 if (kClearPerShot || clear_now) {
-                    uint4 *z = reinterpret_cast<uint4 *>(ibase);
-                    constexpr int nz = (int)(LY::kTail / 16);
-                    for (int i = lane; i < nz; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+                    constexpr int nz = (int)(LY::kTail / 8);
+                    for (int i = lane; i < nz; i += 64) lds_ptr_u64(ibase_addr)[i] = 0ull;
                     clear_now = false;
                 }
                 if (lane < Ws) synl[lane] = syn[shot * Ws + lane];
@@ -303,10 +304,10 @@ void bp_wave_kernel(BPArgs a) {
                     // ---------------- checkpoint of the c->v messages r^(it) (weighted, training)
                     if constexpr (RULE == kRuleWeighted) {
                         if (a.ckpt && it > 0 && it < T && it % a.ckpt_every == 0) {
-                            const uint4 *src = reinterpret_cast<const uint4 *>(ibase + LY::kROff);
-                            uint4 *dst = reinterpret_cast<uint4 *>(
+                            const lds_u64 *src = lds_ptr_u64(ibase_addr + LY::kROff);
+                            uint64_t *dst = reinterpret_cast<uint64_t *>(
                                 a.ckpt + (((size_t)shot * L + l) * a.n_ck + (it / a.ckpt_every - 1)) * (LY::kMsg / 4));
-                            for (int i = lane; i < (int)(LY::kMsg / 16); i += 64) dst[i] = src[i];
+                            for (int i = lane; i < (int)(LY::kMsg / 8); i += 64) dst[i] = src[i];
                         }
                     }
                     // ---------------- variable phase
@@ -418,11 +419,19 @@ void bp_wave_kernel(BPArgs a) {
                     wave_sync();
                 }
             }
+            // the output path recomputes what it derives from the variable ids (hoisting
+            // those per-shot values out of the loops would keep them live, spilled, all along)
+            uint32_t vidc[PV];
+#pragma unroll
+            for (int v = 0; v < PV; ++v) {
+                vidc[v] = vinfo[v];
+                asm volatile("" : "+v"(vidc[v]));
+            }
             if (llr) {
 #pragma unroll
                 for (int v = 0; v < PV; ++v) {
                     const int s = v * 64 + lane;
-                    if (v < vp && s < n) llr[((size_t)shot * L + l) * n + (vinfo[v] & 0xffffu)] = Pl[v];
+                    if (v < vp && s < n) llr[((size_t)shot * L + l) * n + (vidc[v] & 0xffffu)] = Pl[v];
                 }
             }
             // ---------------- output: bit-packed hard decisions via the staging words
@@ -432,14 +441,14 @@ void bp_wave_kernel(BPArgs a) {
             for (int v = 0; v < PV; ++v) {
                 const int s = v * 64 + lane;
                 if (v < vp && s < n && ((decb >> v) & 1u)) {
-                    const uint32_t id = vinfo[v] & 0xffffu;
-                    atomicOr(&stage[id >> 5], 1u << (id & 31));
+                    const uint32_t id = vidc[v] & 0xffffu;
+                    atomicOr((uint32_t *)(stage + (id >> 5)), 1u << (id & 31));
                 }
             }
             wave_sync();
             // representation-major: a work item's records are contiguous (whole-line writes)
             const size_t inst = a.cand_rm ? (size_t)l * a.shots + shot : (size_t)shot * L + l;
-            if (lane < W) cand[inst * W + lane] = reinterpret_cast<const uint64_t *>(stage)[lane];
+            if (lane < W) cand[inst * W + lane] = ((const lds_u64 *)stage)[lane];
             if (lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
             wave_sync();
         }
