@@ -343,15 +343,19 @@ const DualPair kDualPairs[] = {{1, 1}, {2, 1}, {2, 2}, {3, 2}, {3, 3}, {4, 3}, {
 constexpr int kDualMaxChunk = 128;         // shots of a work item (syndromes staged in LDS)
 constexpr int kDualMaxSynBytes = 4096;     // LDS for those syndrome words
 
+bool dual_pick_passes(int pv, int pc, DualPair &out) {
+    for (const DualPair &d : kDualPairs)
+        if (d.pv >= pv && d.pc >= pc) { out = d; return true; }
+    return false;
+}
+
 bool dual_pick(const BPArgs &a, DualPair &out) {
     int pv = 1, pc = 1;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) {
         pv = max(pv, (2 * a.part[p].n + 63) / 64);
         pc = max(pc, (a.part[p].Mmax + 1 + 31) / 32);  // positions of an instance incl. the sink
     }
-    for (const DualPair &d : kDualPairs)
-        if (d.pv >= pv && d.pc >= pc) { out = d; return true; }
-    return false;
+    return dual_pick_passes(pv, pc, out);
 }
 
 template <int PV2, int PC2, int DC, int MAXD, bool LLR>
@@ -400,6 +404,11 @@ bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, in
     stride = ((bytes + 127) & ~127) + 64;
     inst_bytes = 2 * stride + ((a.chunk * a.ws_max * 8 + 15) & ~15);
     return true;
+}
+
+bool bp_dual_fits(int n, int mmax) {
+    DualPair d;
+    return dual_pick_passes((2 * n + 63) / 64, (mmax + 1 + 31) / 32, d);
 }
 
 hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {

@@ -205,6 +205,7 @@ bool bp_layout(const BPArgs &a, int &mpad);
 // Paired form (two instances per wavefront): whether it serves this launch and, if
 // so, the LDS bytes per wavefront.
 bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, int &stride);
+bool bp_dual_fits(int n, int mmax);  // a part of n variables and mmax + 1 positions fits it
 hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s);
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();

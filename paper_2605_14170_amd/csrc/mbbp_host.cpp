@@ -231,8 +231,10 @@ struct HostPart {
     std::vector<uint16_t> lev_chk, ltab;
 };
 
+// pair_hint: launches will run two instances per wavefront where the code fits the
+// paired kernel (its bank-aware layout then targets interleaved lanes).
 mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &bl, const char *name,
-                       HostPart &P) {
+                       HostPart &P, bool pair_hint) {
     const int m = (int)H.size();
     P.m = m; P.n = n; P.H = H;
     if (bl.L < 1) return fail(MBBP_EINVAL, std::string(name) + ": L < 1");
@@ -305,6 +307,8 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
     P.uniform_dc = all6 ? 6 : 0;
     const int L = bl.L, Mmax = P.Mmax;
     const uint16_t sink = (uint16_t)(Mmax * 8);
+    const bool paired = pair_hint && mbbp::bp_dual_fits(n, Mmax);
+    const int lay_group = paired ? 16 : 32;  // variable slots per half-wave of one instance
     P.voff.assign((size_t)L * n * 8, sink);
     P.vid.assign((size_t)L * n, 0);
     P.vdeg.assign((size_t)L * n, 0);
@@ -331,7 +335,7 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             std::vector<std::vector<int>> rows(Ml);
             for (int j = 0; j < Ml; ++j) rows[j].assign(reps[l][j].begin(), reps[l][j].end());
             mbbp::layout::optimize(rows, n, Mmax, 0x5eed0000ull + (uint64_t)l * 7919u + (uint64_t)Mmax, iters,
-                                   lay);
+                                   lay, lay_group, lay_group);
         }
         const std::vector<int32_t> &pos = lay.pos;
         // edges of every variable in ascending check order, as LDS edge ids pos * 8 + slot
@@ -846,8 +850,10 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
         c->params = prm;
         c->HX = hx;
         c->HZ = hz;
-        if ((st = build_part(hz, n, bases->hz, "bases.hz", c->hp[0])) != MBBP_OK) return st;
-        if ((st = build_part(hx, n, bases->hx, "bases.hx", c->hp[1])) != MBBP_OK) return st;
+        const bool pair_hint = prm.rule == MBBP_NMS && schedule == MBBP_FLOODING &&
+                               !(prm.flags & (MBBP_FLAG_FIXED_T | MBBP_FLAG_ONE_PER_WAVE));
+        if ((st = build_part(hz, n, bases->hz, "bases.hz", c->hp[0], pair_hint)) != MBBP_OK) return st;
+        if ((st = build_part(hx, n, bases->hx, "bases.hx", c->hp[1], pair_hint)) != MBBP_OK) return st;
         if (c->hp[0].L != c->hp[1].L) return fail(MBBP_EINVAL, "bases.hx and bases.hz have different L");
         c->LZ = logicals(hx, hz, n);  // ker H_X mod rowspace H_Z
         c->LX = logicals(hz, hx, n);  // ker H_Z mod rowspace H_X

@@ -4,11 +4,15 @@
 // the message of the k-th check of its variable: word k' * S + p, where p is the LDS
 // position of that check and k' its slot in the row.  With S = 1 (mod 64) that word
 // lies in bank (k' + p) mod B.  Lanes of one access that hit the same bank at
-// different words are served one after another.  This annealer chooses the check
-// positions and the variable-to-lane assignment so that, for every pass and k, the
-// lanes spread over the banks: cost = sum over (half-wave, k) of the largest bank
-// multiplicity with 32 banks plus the same over (wave, k) with 64 banks.  It only
-// permutes storage: which check or variable a lane handles never changes any value.
+// different words are served one after another; the LDS serves a wave in two
+// half-waves of 32 lanes over 32 banks.  This annealer chooses the check positions
+// and the variable-to-lane assignment so that, for every half-wave and k, the lanes
+// spread over the banks: cost = sum over (group of G consecutive variable slots, k)
+// of the largest multiplicity over B banks.  One instance per wavefront: a half-wave
+// is 32 slots, G = B = 32.  Two interleaved instances per wavefront: a half-wave
+// holds 16 slots of each instance and the two copies of a row lie 16 banks apart,
+// so G = B = 16.  It only permutes storage: which check or variable a lane handles
+// never changes any value.
 #pragma once
 
 #include <algorithm>
@@ -42,9 +46,9 @@ struct Result {
 // degree (descending, stable); moves keep every pass's degree profile: two
 // variables swap lanes when they are in the same pass or have the same degree.
 inline void optimize(const std::vector<std::vector<int>> &rows, int n, int npos, uint64_t seed, long iters,
-                     Result &out) {
+                     Result &out, int G = 32, int B = 32) {
     const int M = (int)rows.size();
-    const int P = (n + 63) / 64;
+    const int NG = (n + G - 1) / G;  // slot groups
     std::vector<std::vector<std::pair<int, int>>> ve(n);  // (check, row slot), ascending check
     for (int j = 0; j < M; ++j)
         for (int k = 0; k < (int)rows[j].size(); ++k) ve[rows[j][k]].push_back({j, k});
@@ -57,28 +61,23 @@ inline void optimize(const std::vector<std::vector<int>> &rows, int n, int npos,
     std::vector<int32_t> pos(M), at(npos, -1);
     for (int j = 0; j < M; ++j) { pos[j] = j; at[j] = j; }
     const int K = 8;
-    std::vector<uint8_t> c32((size_t)P * 2 * K * 32, 0), c64((size_t)P * K * 64, 0);
+    std::vector<uint8_t> cnt((size_t)NG * K * B, 0);
     auto add_var = [&](int i, int d) {
         const int s = slot_of[i];
         for (int k = 0; k < deg[i]; ++k) {
-            const uint32_t b = (uint32_t)(ve[i][k].second + pos[ve[i][k].first]);
-            c32[((size_t)(s >> 5) * K + k) * 32 + (b & 31)] += (uint8_t)d;
-            c64[((size_t)(s >> 6) * K + k) * 64 + (b & 63)] += (uint8_t)d;
+            const int b = (ve[i][k].second + pos[ve[i][k].first]) % B;
+            cnt[((size_t)(s / G) * K + k) * B + b] += (uint8_t)d;
         }
     };
-    auto mx = [](const uint8_t *c, int B) {
+    auto keycost = [&](int key) {
+        const uint8_t *c = &cnt[(size_t)key * B];
         int m = 0;
         for (int b = 0; b < B; ++b) m = std::max(m, (int)c[b]);
         return m;
     };
-    auto keycost = [&](int key) {
-        const int gk = key & 0xfffff;
-        return (key >> 20) == 0 ? mx(&c32[(size_t)gk * 32], 32) : mx(&c64[(size_t)gk * 64], 64);
-    };
     for (int i = 0; i < n; ++i) add_var(i, 1);
     long cost = 0, ideal = 0;
-    for (int g = 0; g < P * 2 * K; ++g) { const int m = mx(&c32[(size_t)g * 32], 32); cost += m; ideal += m > 0; }
-    for (int g = 0; g < P * K; ++g) { const int m = mx(&c64[(size_t)g * 64], 64); cost += m; ideal += m > 0; }
+    for (int g = 0; g < NG * K; ++g) { const int m = keycost(g); cost += m; ideal += m > 0; }
     out.cost_before = cost;
     out.ideal = ideal;
     Rng rng(seed);
@@ -102,7 +101,7 @@ inline void optimize(const std::vector<std::vector<int>> &rows, int n, int npos,
             s1 = (int)rng.below((uint32_t)n);
             s2 = (int)rng.below((uint32_t)n);
             if (s1 == s2) continue;
-            if ((s1 >> 6) != (s2 >> 6) && deg[sv[s1]] != deg[sv[s2]]) continue;
+            if (s1 / (2 * G) != s2 / (2 * G) && deg[sv[s1]] != deg[sv[s2]]) continue;  // keep pass profiles
             vars.push_back(sv[s1]);
             vars.push_back(sv[s2]);
         }
@@ -111,10 +110,7 @@ inline void optimize(const std::vector<std::vector<int>> &rows, int n, int npos,
         auto collect = [&]() {
             for (int v : vars) {
                 const int s = slot_of[v];
-                for (int k = 0; k < deg[v]; ++k) {
-                    keys.push_back((s >> 5) * K + k);
-                    keys.push_back((1 << 20) | ((s >> 6) * K + k));
-                }
+                for (int k = 0; k < deg[v]; ++k) keys.push_back((s / G) * K + k);
             }
         };
         auto apply = [&](bool fwd) {
