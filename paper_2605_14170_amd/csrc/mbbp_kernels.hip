@@ -235,33 +235,46 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
 
 // One thread per shot.  Part X: residual r = e_X ^ corr_x fails iff H_Z r != 0 or
 // L_Z r != 0 (it is then not a product of X stabilizers); part Z symmetric.
-// part[0] holds H_Z and L_Z, part[1] holds H_X and L_X.
-__global__ __launch_bounds__(256) void fail_kernel(FailArgs a) {
-    const int64_t shot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// part[0] holds H_Z and L_Z, part[1] holds H_X and L_X.  The residual words are
+// read from memory once and staged in LDS as [word][thread] (the row loop's
+// column indices are block-uniform, so the reads are conflict-free).
+constexpr int kFailBlock = 256;
+__global__ __launch_bounds__(kFailBlock) void fail_kernel(FailArgs a) {
+    __shared__ uint64_t sh_r[kMaxWords][kFailBlock];
+    const int t = threadIdx.x;
+    const int64_t shot = (int64_t)blockIdx.x * blockDim.x + t;
     long long c_fail = 0, c_fx = 0, c_fz = 0, c_kmax = 0;
-    if (shot < a.shots) {
-        uint32_t flags = 0;
-        for (int pt = 0; pt < 2; ++pt) {
-            const DevPart &P = a.part[pt];
-            const int W = P.W;
+    const bool live = shot < a.shots;
+    uint32_t flags = 0;
+    for (int pt = 0; pt < 2; ++pt) {
+        const DevPart &P = a.part[pt];
+        const int W = P.W;
+        __syncthreads();
+        if (live) {
             const uint64_t *e = a.err[pt] + (size_t)shot * W;
             const uint64_t *c = a.corr[pt] + (size_t)shot * W;
+            for (int w = 0; w < W; ++w) sh_r[w][t] = e[w] ^ c[w];
+        }
+        __syncthreads();
+        if (live) {
             bool bad = false;
             for (int j = 0; j < P.m && !bad; ++j) {
                 uint32_t par = 0;
                 for (int k = P.hrow_ptr[j]; k < P.hrow_ptr[j + 1]; ++k) {
                     const int col = P.hrow_idx[k];
-                    par ^= (uint32_t)((e[col >> 6] ^ c[col >> 6]) >> (col & 63)) & 1u;
+                    par ^= (uint32_t)(sh_r[col >> 6][t] >> (col & 63)) & 1u;
                 }
                 bad = par != 0;
             }
             for (int r = 0; r < P.k && !bad; ++r) {
                 int cnt = 0;
-                for (int w = 0; w < W; ++w) cnt += __popcll((e[w] ^ c[w]) & P.logical[(size_t)r * W + w]);
+                for (int w = 0; w < W; ++w) cnt += __popcll(sh_r[w][t] & P.logical[(size_t)r * W + w]);
                 bad = (cnt & 1) != 0;
             }
             if (bad) flags |= 1u << pt;
         }
+    }
+    if (live) {
         if (a.fail) a.fail[shot] = (uint8_t)flags;
         c_fail = flags != 0;
         c_fx = flags & 1u;
