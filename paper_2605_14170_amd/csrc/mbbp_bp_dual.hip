@@ -57,7 +57,8 @@ constexpr uint64_t kLanes0 = 0x5555555555555555ull;  // lanes of instance 0
 template <int PV2, int PC2, int DC, int MAXD, bool LLR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void bp_dual_kernel(BPArgs a) {
-    using LY = LayoutM<32 * PC2, kRuleNMS, DC, false>;
+    using LY = LayoutM<32 * PC2, kRuleNMS, DC, false, true>;  // slot pairs
+    static_assert(DC % 2 == 0 && LY::S % 16 == 1, "slot pairs");
     constexpr int S = LY::S;
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
@@ -174,9 +175,9 @@ void bp_dual_kernel(BPArgs a) {
                 if ((fresh >> comp) & 1u) {
 #pragma unroll
                     for (int c = 0; c < PC2; ++c) {
-                        lds_f32 *row = lds_ptr_f32(cbase_addr + 4u * (uint32_t)(c * 32 + half));
+                        const uint32_t row = cbase_addr + 8u * (uint32_t)(c * 32 + half);
 #pragma unroll
-                        for (int k = 0; k < DC; ++k) row[k * S] = 0.0f;
+                        for (int u = 0; u < DC / 2; ++u) *lds_ptr_u64(row + 8u * (uint32_t)(u * S)) = 0ull;
                     }
                 }
                 wave_sync();
@@ -238,16 +239,20 @@ void bp_dual_kernel(BPArgs a) {
 #pragma unroll
             for (int c = 0; c < PC2; ++c) {
                 const int p = c * 32 + half;
-                const lds_f32 *row = lds_ptr_f32(cbase_addr + 4u * (uint32_t)p);
+                const uint32_t row = cbase_addr + 8u * (uint32_t)p;  // slot pair u at + 8 u S
 #pragma unroll
-                for (int k = 0; k < DC; ++k) qa[c][k] = row[k * S];
+                for (int u = 0; u < DC / 2; ++u) {
+                    const f32x2 w = *lds_ptr_f32x2(row + 8u * (uint32_t)(u * S));
+                    qa[c][2 * u] = w.x;
+                    qa[c][2 * u + 1] = w.y;
+                }
                 const uint64_t dw = *lds_ptr_u64(cbase_addr + LY::kDecOff + 8u * (uint32_t)p);
                 unsat |= (row_parity(dw) ^ (sbits >> c)) & ((rowv >> c) & 1u);
             }
 #pragma unroll
             for (int c = 0; c < PC2; ++c) {
                 const int p = c * 32 + half;
-                lds_f32 *row = lds_ptr_f32(cbase_addr + 4u * (uint32_t)p);
+                const uint32_t row = cbase_addr + 8u * (uint32_t)p;
                 float (&q)[DC] = qa[c];
                 if constexpr (DC == 8) {
                     const int w = (int)cwp[c];
@@ -257,7 +262,12 @@ void bp_dual_kernel(BPArgs a) {
                 }
                 CheckRule<kRuleNMS>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
 #pragma unroll
-                for (int k = 0; k < DC; ++k) row[k * S] = q[k];
+                for (int u = 0; u < DC / 2; ++u) {
+                    f32x2 w;
+                    w.x = q[2 * u];
+                    w.y = q[2 * u + 1];
+                    *lds_ptr_f32x2(row + 8u * (uint32_t)(u * S)) = w;
+                }
             }
             // ---------------- halting of each instance (Section II-B)
             const uint64_t ub = __ballot(unsat != 0u);

@@ -209,7 +209,10 @@ struct WeightedRule {
 // half and its decision byte's address in the high half (LDS addresses fit 16 bits).
 // Junk positions are unused by representation l; position Mmax (of the part) is the
 // sink of absent edges.
-template <int MPAD, int RULE, int DC, bool COMPACT>
+// PAIRS (the paired kernel): messages in slot pairs, edge (p, k) at word
+// (k >> 1) * 2S + 2p + (k & 1), so a check lane moves two slots of its row with one
+// 8-byte access; with S = 1 (mod 16) its bank is (2 (p + (k >> 1)) + (k & 1)) mod 32.
+template <int MPAD, int RULE, int DC, bool COMPACT, bool PAIRS = false>
 struct LayoutM {
     static constexpr bool kCompact = COMPACT;
     static constexpr int kSlots = kCompact ? DC : 8;
@@ -225,7 +228,9 @@ struct LayoutM {
     __device__ __forceinline__ static uint32_t dec(uint32_t ea) { return ea >> 16; }
     // packed edge word of edge id e = position * 8 + slot
     __device__ __forceinline__ static uint32_t edge_word(uint32_t ibase_addr, uint32_t e) {
-        const uint32_t m = ibase_addr + 4u * ((e & 7u) * (uint32_t)S + (e >> 3));
+        const uint32_t k = e & 7u, p = e >> 3;
+        const uint32_t m =
+            ibase_addr + 4u * (PAIRS ? (k >> 1) * 2u * (uint32_t)S + 2u * p + (k & 1u) : k * (uint32_t)S + p);
         const uint32_t d = ibase_addr + kDecOff + 8u * (e >> 3) + (e & 7u);
         return m | (d << 16);
     }

@@ -335,7 +335,7 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             std::vector<std::vector<int>> rows(Ml);
             for (int j = 0; j < Ml; ++j) rows[j].assign(reps[l][j].begin(), reps[l][j].end());
             mbbp::layout::optimize(rows, n, Mmax, 0x5eed0000ull + (uint64_t)l * 7919u + (uint64_t)Mmax, iters,
-                                   lay, lay_group, lay_group);
+                                   lay, lay_group, lay_group, paired);
         }
         const std::vector<int32_t> &pos = lay.pos;
         // edges of every variable in ascending check order, as LDS edge ids pos * 8 + slot

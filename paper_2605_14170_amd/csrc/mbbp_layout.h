@@ -45,8 +45,10 @@ struct Result {
 // rows[j]: variables of check j (in row-slot order).  Variables start sorted by
 // degree (descending, stable); moves keep every pass's degree profile: two
 // variables swap lanes when they are in the same pass or have the same degree.
+// pairs: messages stored in slot pairs (edge (p, k) at word (k >> 1) * 2S + 2p + (k & 1),
+// S = 1 mod 16), so the bank is 2 (p + (k >> 1)) + (k & 1) instead of k + p.
 inline void optimize(const std::vector<std::vector<int>> &rows, int n, int npos, uint64_t seed, long iters,
-                     Result &out, int G = 32, int B = 32) {
+                     Result &out, int G = 32, int B = 32, bool pairs = false) {
     const int M = (int)rows.size();
     const int NG = (n + G - 1) / G;  // slot groups
     std::vector<std::vector<std::pair<int, int>>> ve(n);  // (check, row slot), ascending check
@@ -65,7 +67,8 @@ inline void optimize(const std::vector<std::vector<int>> &rows, int n, int npos,
     auto add_var = [&](int i, int d) {
         const int s = slot_of[i];
         for (int k = 0; k < deg[i]; ++k) {
-            const int b = (ve[i][k].second + pos[ve[i][k].first]) % B;
+            const int t = ve[i][k].second, p = pos[ve[i][k].first];
+            const int b = (pairs ? 2 * (p + (t >> 1)) + (t & 1) : t + p) % B;
             cnt[((size_t)(s / G) * K + k) * B + b] += (uint8_t)d;
         }
     };

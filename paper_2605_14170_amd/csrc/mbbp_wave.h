@@ -51,10 +51,13 @@ typedef __attribute__((address_space(3))) float lds_f32;
 typedef __attribute__((address_space(3))) unsigned char lds_u8;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) f32x2 lds_f32x2;
 
 __device__ __forceinline__ lds_f32 *lds_ptr_f32(uint32_t byte_addr) { return (lds_f32 *)(size_t)byte_addr; }
 __device__ __forceinline__ lds_u8 *lds_ptr_u8(uint32_t byte_addr) { return (lds_u8 *)(size_t)byte_addr; }
 __device__ __forceinline__ lds_u64 *lds_ptr_u64(uint32_t byte_addr) { return (lds_u64 *)(size_t)byte_addr; }
 __device__ __forceinline__ lds_u32 *lds_ptr_u32(uint32_t byte_addr) { return (lds_u32 *)(size_t)byte_addr; }
+__device__ __forceinline__ lds_f32x2 *lds_ptr_f32x2(uint32_t byte_addr) { return (lds_f32x2 *)(size_t)byte_addr; }
 
 }  // namespace mbbp

@@ -7,7 +7,8 @@ and that its reported cost is the bank model it claims to minimise, recomputed h
 independently in Python:
 cost = sum over (group of G consecutive variable slots, k) of the largest number of
 those slots whose k-th edge (ascending check order) lies in one bank, where edge
-(check j, row slot t) at position p sits in bank (t + p) mod B.
+(check j, row slot t) at position p is word t * S + p (slot pairs: (t >> 1) * 2S +
+2p + (t & 1)) of the message array, in bank word mod B.
 """
 
 import json
@@ -29,12 +30,12 @@ DRIVER = r'''
 #include <cstdio>
 #include <iostream>
 int main() {
-    int n, M, npos, G, B; long iters; unsigned long long seed;
-    std::cin >> n >> M >> npos >> G >> B >> iters >> seed;
+    int n, M, npos, G, B, pairs; long iters; unsigned long long seed;
+    std::cin >> n >> M >> npos >> G >> B >> pairs >> iters >> seed;
     std::vector<std::vector<int>> rows(M);
     for (auto &r : rows) { int w; std::cin >> w; r.resize(w); for (int &x : r) std::cin >> x; }
     mbbp::layout::Result out;
-    mbbp::layout::optimize(rows, n, npos, seed, iters, out, G, B);
+    mbbp::layout::optimize(rows, n, npos, seed, iters, out, G, B, pairs != 0);
     printf("{\"before\": %ld, \"after\": %ld, \"ideal\": %ld, \"pos\": [", out.cost_before, out.cost_after, out.ideal);
     for (size_t i = 0; i < out.pos.size(); ++i) printf("%s%d", i ? "," : "", out.pos[i]);
     printf("], \"slot_var\": [");
@@ -57,14 +58,14 @@ def driver():
     shutil.rmtree(d, ignore_errors=True)
 
 
-def run(exe, rows, n, npos, G, B, iters=3000, seed=12345):
-    txt = f"{n} {len(rows)} {npos} {G} {B} {iters} {seed}\n" + "".join(
+def run(exe, rows, n, npos, G, B, iters=3000, seed=12345, pairs=False):
+    txt = f"{n} {len(rows)} {npos} {G} {B} {int(pairs)} {iters} {seed}\n" + "".join(
         f"{len(r)} " + " ".join(map(str, r)) + "\n" for r in rows)
     res = subprocess.run([exe], input=txt, capture_output=True, text=True, check=True)
     return json.loads(res.stdout)
 
 
-def bank_cost(rows, n, pos, slot_var, G, B):
+def bank_cost(rows, n, pos, slot_var, G, B, pairs=False):
     edges = [[] for _ in range(n)]  # (check, row slot), ascending check
     for j, r in enumerate(rows):
         for t, v in enumerate(r):
@@ -77,7 +78,8 @@ def bank_cost(rows, n, pos, slot_var, G, B):
                 e = edges[slot_var[s]]
                 if k < len(e):
                     j, t = e[k]
-                    cnt[(t + pos[j]) % B] += 1
+                    word = (t >> 1) * 2 * 97 + 2 * pos[j] + (t & 1) if pairs else t * 97 + pos[j]
+                    cnt[word % B] += 1
             cost += int(cnt.max())
     return cost
 
@@ -112,13 +114,14 @@ def test_layout_is_a_valid_permutation_keeping_pass_profiles(driver, G, B):
         assert sorted(deg[sv[p0:p0 + 2 * G]]) == sorted(deg[start[p0:p0 + 2 * G]])
 
 
-@pytest.mark.parametrize("G,B", [(32, 32), (16, 16)])
-def test_layout_cost_is_the_bank_model_and_does_not_grow(driver, G, B):
+@pytest.mark.parametrize("G,B,pairs", [(32, 32, False), (16, 16, False), (16, 16, True)])
+def test_layout_cost_is_the_bank_model_and_does_not_grow(driver, G, B, pairs):
     rows, n = representation(2)
     M = len(rows)
     npos = 32 * ((M + 1 + 31) // 32) - 1
-    out = run(driver, rows, n, npos, G, B)
-    assert out["after"] == bank_cost(rows, n, out["pos"], out["slot_var"], G, B)
+    out = run(driver, rows, n, npos, G, B, pairs=pairs)
+    # banks from the actual word index with slot stride S = 97 (1 mod 32; 1 mod 16)
+    assert out["after"] == bank_cost(rows, n, out["pos"], out["slot_var"], G, B, pairs)
     assert out["after"] <= out["before"]
     # the identity layout (checks in row order, variables degree-sorted) is the start
     deg = np.zeros(n, int)
@@ -126,7 +129,7 @@ def test_layout_cost_is_the_bank_model_and_does_not_grow(driver, G, B):
         for v in r:
             deg[v] += 1
     start = sorted(range(n), key=lambda v: -deg[v])
-    assert out["before"] == bank_cost(rows, n, list(range(M)), start, G, B)
+    assert out["before"] == bank_cost(rows, n, list(range(M)), start, G, B, pairs)
     # a lower bound: every (group, k) with an edge costs at least 1
     assert out["after"] >= out["ideal"]
 
