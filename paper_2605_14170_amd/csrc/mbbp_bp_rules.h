@@ -262,9 +262,9 @@ __device__ __forceinline__ float excl_sums(const float (&r)[D], float mu, float 
 // Variable rule (eq. (2) and the posterior of Section II-B) for a variable of
 // degree deg <= D (edges k >= deg point at the sink and read as 0): reads the c->v
 // messages at msg(ea) + ROFF, writes every q_k at msg(ea) and the hard decision at
-// dec(ea).  prev is the decision already stored in the cells: when no active lane
-// changed its decision the cell stores are skipped (called by every lane that holds
-// a variable of the pass).
+// dec(ea).  prev is the decision already stored in the cells: only lanes whose
+// decision changed store it (the fewer lanes a byte store carries, the fewer of them
+// share an LDS bank), and the stores are skipped when no lane changed.
 template <int D, typename LY>
 __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, float &P, bool &dec) {
     constexpr uint32_t ROFF = LY::kROff;
@@ -280,7 +280,7 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     P = pre;
 #pragma unroll
     for (int k = 0; k < D; ++k) *lds_ptr_f32(LY::msg(ea[k])) = q[k];
-    if (__ballot(dec != prev) != 0ull) {
+    if (dec != prev) {
 #pragma unroll
         for (int k = 0; k < D; ++k) *lds_ptr_u8(LY::dec(ea[k])) = (unsigned char)dec;
     }
