@@ -28,6 +28,7 @@ ORC_OK, ORC_EINVAL, ORC_ENOTINROWSPACE, ORC_ENOMEM = 0, -1, -2, -3
 
 FLOODING, LAYERED = 0, 1
 NMS, SPA, WNMS = 0, 1, 2
+DEPOLARIZING, BSC_X = 0, 1  # noise models of sample()
 MIN_WEIGHT, FWS = 0, 1
 
 
@@ -67,7 +68,7 @@ def _declare(lib: ctypes.CDLL) -> None:
     i32, i64, u64, dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     lib.orc_philox4x64_10.argtypes = [_P, _P, _P]
     lib.orc_philox4x64_10.restype = None
-    lib.orc_sample.argtypes = [i32, i32, _P, _P, i32, _P, _P, u64, dbl, i64, i64, _P, _P, _P, _P]
+    lib.orc_sample.argtypes = [i32, i32, _P, _P, i32, _P, _P, u64, dbl, i32, i64, i64, _P, _P, _P, _P]
     lib.orc_rank.argtypes = [i32, i32, _P, _P]
     lib.orc_subtrees.argtypes = [i32, i32, _P, _P, _P, _P, _P, _P]
     lib.orc_build_bases.argtypes = [i32, i32, _P, _P, i32, i32, i32, _P, _P, _P, i32]
@@ -117,8 +118,11 @@ def philox4x64_10(ctr: Sequence[int], key: Sequence[int], precision: str = "f64"
     return out
 
 
-def sample(hx: np.ndarray, hz: np.ndarray, seed: int, p: float, shot0: int, shots: int):
-    """Depolarizing errors and syndromes for shots [shot0, shot0 + shots).
+def sample(hx: np.ndarray, hz: np.ndarray, seed: int, p: float, shot0: int, shots: int,
+           noise: int = DEPOLARIZING):
+    """Errors and syndromes for shots [shot0, shot0 + shots): depolarizing (X, Y, Z
+    each with probability p/3), or BSC_X (X errors only, each qubit flipped with
+    probability p: the noise of the paper's experiments, Section IV).
     Returns (e_x, e_z, s_x, s_z) as bit-packed uint64 arrays, named by error
     type: s_x = H_Z e_x (m_Z bits), s_z = H_X e_z (m_X bits)."""
     lib = _lib("f64")
@@ -131,7 +135,7 @@ def sample(hx: np.ndarray, hz: np.ndarray, seed: int, p: float, shot0: int, shot
     sx = np.zeros((shots, wz), np.uint64)
     sz = np.zeros((shots, wx), np.uint64)
     _check(lib.orc_sample(n, hx.shape[0], _ptr(xp), _ptr(xi), hz.shape[0], _ptr(zp), _ptr(zi),
-                          int(seed), float(p), int(shot0), int(shots),
+                          int(seed), float(p), int(noise), int(shot0), int(shots),
                           _ptr(ex), _ptr(ez), _ptr(sx), _ptr(sz)), "sample")
     return ex, ez, sx, sz
 
@@ -282,10 +286,11 @@ def failures(stab: np.ndarray, err: np.ndarray, corr: np.ndarray) -> np.ndarray:
     return out.astype(bool)
 
 
-def prior_llr(p: float) -> float:
-    """Per-type prior LLR under depolarizing noise: each of X and Z parts flips
-    with probability 2p/3 (BP initialisation of Section II-B)."""
-    q = 2.0 * p / 3.0
+def prior_llr(p: float, noise: int = DEPOLARIZING) -> float:
+    """Per-type prior LLR (BP initialisation of Section II-B): ln((1 - q) / q) with
+    q = 2p/3 under depolarizing noise (each of the X and Z parts flips with that
+    probability) and q = p under X-only noise (the binary symmetric channel)."""
+    q = p if noise == BSC_X else 2.0 * p / 3.0
     return float(np.log((1.0 - q) / q))
 
 
@@ -318,11 +323,12 @@ class RunResult:
 
 def run(code, bases_x, bases_z, seed: int, p: float, shot0: int, shots: int, T: int,
         alpha: float, schedule: int = FLOODING, rule: int = NMS, select_rule: int = MIN_WEIGHT,
-        rmax: float = 65536.0, precision: str = "f64") -> RunResult:
+        rmax: float = 65536.0, precision: str = "f64", noise: int = DEPOLARIZING) -> RunResult:
     """The whole path on the CPU for a shot range: sample, decode both types,
-    select, failure test, counters.  bases_* = (basis_ptr, rows)."""
-    ex, ez, sx, sz = sample(code.hx, code.hz, seed, p, shot0, shots)
-    mu = prior_llr(p)
+    select, failure test, counters.  bases_* = (basis_ptr, rows).  Both parts
+    take the prior of the noise model (under X-only noise part Z sees no errors)."""
+    ex, ez, sx, sz = sample(code.hx, code.hz, seed, p, shot0, shots, noise)
+    mu = prior_llr(p, noise)
     mu32 = float(np.float32(mu))
     n = code.n
     fails = np.zeros(shots, bool)

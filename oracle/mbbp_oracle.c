@@ -24,8 +24,9 @@
  *                         r^(t) = clamp((1 - beta) * S * alpha * M + beta * r^(t-1)),
  *                         r^(0) = 0 (rule 2 of orc_decode, flooding only)
  *   - orc_failures      : logical failure = residual not a stabilizer (Section II-A)
- *   - orc_philox4x64_10 / orc_sample : counter-based depolarizing noise (Philox,
- *                         Salmon et al., SC'11), syndromes s = H e
+ *   - orc_philox4x64_10 / orc_sample : counter-based noise (Philox, Salmon et al.,
+ *                         SC'11), syndromes s = H e: depolarizing, or X errors only
+ *                         (binary symmetric channel, the noise of Section IV)
  *
  * Conventions (readings where the paper is silent):
  *   - Syndrome BP: the check message carries the factor (-1)^{s_j}.
@@ -101,13 +102,16 @@ static int parity_row(const int *cols, int len, const uint64_t *e) {
 
 /* Qubit q of shot s takes the 32-bit half (q % 2) of output word (q % 8) / 2 of
  * philox(counter = (s, q / 8, 0, 0), key = (seed, 0)).                         */
+/* noise 0: depolarizing (thresholds above); noise 1: X errors only, qubit q
+ * flipped iff u < floor(p * 2^32), e_Z = 0.                                     */
 int orc_sample(int n, int mx, const int *hx_ptr, const int *hx_idx,
                int mz, const int *hz_ptr, const int *hz_idx,
-               uint64_t seed, double p, int64_t shot0, int64_t shots,
+               uint64_t seed, double p, int noise, int64_t shot0, int64_t shots,
                uint64_t *ex, uint64_t *ez, uint64_t *sx, uint64_t *sz) {
-    if (n <= 0 || p < 0.0 || p > 1.0 || shots < 0) return ORC_EINVAL;
+    if (n <= 0 || p < 0.0 || p > 1.0 || shots < 0 || (noise != 0 && noise != 1)) return ORC_EINVAL;
     uint64_t t[3];
     thresholds(p, t);
+    const uint64_t tb = (uint64_t)floor(p * 4294967296.0);
     int wn = words64(n), wx = words64(mx), wz = words64(mz);
     for (int64_t s = 0; s < shots; ++s) {
         uint64_t *exs = ex + s * wn, *ezs = ez + s * wn;
@@ -125,7 +129,9 @@ int orc_sample(int n, int mx, const int *hx_ptr, const int *hx_idx,
             }
             int sub = q % 8;
             uint64_t u = (block[sub / 2] >> (32 * (sub % 2))) & 0xFFFFFFFFULL;
-            if (u < t[0]) {            /* X */
+            if (noise == 1) {
+                if (u < tb) setbit(exs, q);
+            } else if (u < t[0]) {     /* X */
                 setbit(exs, q);
             } else if (u < t[1]) {     /* Y = X and Z */
                 setbit(exs, q);

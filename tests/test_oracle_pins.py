@@ -99,6 +99,51 @@ def test_sampler_frequencies():
         assert abs(cnt - mean) < 5 * np.sqrt(mean * (1 - p / 3))
 
 
+def test_sampler_x_only_against_numpy_philox():
+    """X-only noise (the binary symmetric channel of Section IV): qubit q flipped iff
+    its Philox word u < floor(p 2^32) (exact rational floor), no Z errors, s_z = 0."""
+    code = codes.bb144()
+    seed, p, shot0, shots = 3, 0.07, 55, 30
+    ex, ez, sx, sz = oracle.sample(code.hx, code.hz, seed, p, shot0, shots, noise=oracle.BSC_X)
+    n = code.n
+    tb = (Fraction(p) * 2**32).__floor__()
+    bx = np.zeros((shots, n), np.uint8)
+    for s in range(shots):
+        for b in range((n + 7) // 8):
+            out = _numpy_philox_block([shot0 + s, b, 0, 0], [seed, 0])
+            for sub in range(8):
+                q = 8 * b + sub
+                if q < n:
+                    bx[s, q] = ((int(out[sub // 2]) >> (32 * (sub % 2))) & 0xFFFFFFFF) < tb
+    np.testing.assert_array_equal(oracle.unpack(ex, n), bx)
+    assert not ez.any() and not sz.any()
+    np.testing.assert_array_equal(oracle.unpack(sx, code.hz.shape[0]),
+                                  (bx.astype(np.int64) @ code.hz.T.astype(np.int64)) % 2)
+
+
+def test_sampler_x_only_is_the_depolarizing_x_part():
+    """With p_x = 2 p / 3 exact (p = 0.75: both thresholds are 2^31) the X-only
+    errors are exactly the X parts (X or Y) of the depolarizing errors."""
+    code = codes.bb72()
+    dep = oracle.sample(code.hx, code.hz, 9, 0.75, 100, 50)
+    bsc = oracle.sample(code.hx, code.hz, 9, 0.5, 100, 50, noise=oracle.BSC_X)
+    np.testing.assert_array_equal(bsc[0], dep[0])
+    np.testing.assert_array_equal(bsc[2], dep[2])
+
+
+def test_sampler_x_only_frequency_and_prior():
+    code = codes.bb144()
+    p, shots = 0.04, 20000
+    ex, _, _, _ = oracle.sample(code.hx, code.hz, 11, p, 0, shots, noise=oracle.BSC_X)
+    cnt = int(oracle.unpack(ex, code.n).sum())
+    mean = code.n * shots * p
+    assert abs(cnt - mean) < 5 * np.sqrt(mean * (1 - p))
+    # prior LLR of the binary symmetric channel, log((1 - p) / p), against the
+    # depolarizing one at the rate with the same flip probability (2 p'/3 = p)
+    assert oracle.prior_llr(p, oracle.BSC_X) == pytest.approx(np.log(0.96 / 0.04), rel=1e-15)
+    assert oracle.prior_llr(p, oracle.BSC_X) == pytest.approx(oracle.prior_llr(1.5 * p), rel=1e-12)
+
+
 # ------------------------------------------------------------------ codes and GF(2)
 
 @pytest.mark.parametrize("factory,k", [(codes.bb72, 12), (codes.bb144, 12), (codes.bb288, 12),
