@@ -58,6 +58,12 @@ def parse():
     ap.add_argument("--lr", type=float, default=1e-3, help="weighted workload: Adam learning rate")
     ap.add_argument("--val-every", type=int, default=100, help="weighted workload: validate every k steps (0: off)")
     ap.add_argument("--val-shots", type=int, default=200_000, help="weighted workload: validation shots")
+    ap.add_argument("--paper-ler", action="store_true",
+                    help="logical error rates under the paper's conditions (Section IV): X errors only, "
+                         "layered schedule, T = 100, FWS decision, 100 failures per point")
+    ap.add_argument("--ler-ps", default="0.03,0.04,0.05,0.06,0.07,0.08", help="--paper-ler: error rates")
+    ap.add_argument("--ler-failures", type=int, default=100, help="--paper-ler: failures per point")
+    ap.add_argument("--ler-max-shots", type=int, default=50_000_000, help="--paper-ler: shot cap per point")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -135,6 +141,47 @@ def wilson(k, n, z=1.959963984540054):
     c = (ph + z * z / (2 * n)) / den
     h = z * math.sqrt(ph * (1 - ph) / n + z * z / (4 * n * n)) / den
     return (max(0.0, c - h), min(1.0, c + h))
+
+
+def paper_ler_main(args, wl, code):
+    """The paper's experimental conditions (Section IV) on this workload's code and
+    bases: X errors only (binary symmetric channel), normalized min-sum with
+    alpha = 0.875, layered schedule, at most 100 iterations, FWS decision; at each p,
+    batches of shots until the failure count reaches --ler-failures.  One JSON line
+    per p (context for the paper's LER curves, not a throughput figure)."""
+    import torch
+    import paper_2605_14170_amd as pk
+    batch = args.shots or 1_000_000
+    torch.cuda.set_device(0)
+    from workloads.perms import check_permutations
+    perms = lambda h: check_permutations(h.shape[0], max(wl.L, 8), wl.perm_seed)  # noqa: E731
+    bx = pk.build_bases(code.hx, wl.basis_mode, wl.L, perms(code.hx))
+    bz = pk.build_bases(code.hz, wl.basis_mode, wl.L, perms(code.hz))
+    dec = pk.Decoder(code.hx, code.hz, bx, bz, 100, schedule=pk.LAYERED, alpha=0.875, select=pk.FWS,
+                     max_batch=batch)
+    dec.set_noise(pk.X_ONLY)
+    for i, p in enumerate(float(x) for x in args.ler_ps.split(",")):
+        c = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
+        shots = 0
+        t0 = time.perf_counter()
+        while shots < args.ler_max_shots:
+            dec.run(wl.seed, p, (i << 40) + shots, batch, c)
+            shots += batch
+            if int(c[pk.CNT_FAIL]) >= args.ler_failures:
+                break
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cc = c.cpu().numpy()
+        f = int(cc[pk.CNT_FAIL])
+        lo, hi = wilson(f, shots)
+        print(json.dumps(dict(workload=wl.key, code=wl.key.split("_")[0], noise="x_only", schedule="layered",
+                              T=100, alpha=0.875, decision="FWS", L=wl.L, basis_mode=wl.basis_mode, p=p,
+                              shots=shots, failures=f, ler=f / shots, ler_95=[lo, hi],
+                              mean_kmax=float(cc[pk.CNT_SUM_KMAX]) / shots,
+                              # part Z sees no errors (K = 0 there): mean iterations of part X
+                              mean_k=float(cc[pk.CNT_SUM_K]) / (wl.L * shots),
+                              noconv=int(cc[pk.CNT_NOCONV]), seconds=round(dt, 3))), flush=True)
+    dec.close()
 
 
 def weighted_main(args, wl, code):
@@ -274,6 +321,8 @@ def main():
     code = wl.code()
     if "weighted" in wl.key:
         return weighted_main(args, wl, code)
+    if args.paper_ler:
+        return paper_ler_main(args, wl, code)
     shots = args.shots or wl.shots
     torch.cuda.set_device(0)
     dec, bx, bz = build_decoder(pk, wl, code, shots)

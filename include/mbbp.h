@@ -139,11 +139,20 @@ mbbp_status mbbp_decode_detail(mbbp_ctx *ctx, int32_t part, int64_t shots, const
                                const float *prior, int32_t prior_per_shot,
                                uint64_t *cand, uint16_t *kstat, float *llr, void *hip_stream);
 
-/* Counter-based depolarizing noise (code-capacity: X, Y, Z each with probability
- * p/3): qubit q of shot s uses the 32-bit half (q%2) of word (q%8)/2 of
- * Philox4x64-10(counter = (s, q/8, 0, 0), key = (seed, 0)) [Salmon et al. SC'11];
+/* Noise models of mbbp_sample, mbbp_run and mbbp_autotune (per context, set with
+ * mbbp_set_noise; default MBBP_NOISE_DEPOLARIZING).  MBBP_NOISE_X_ONLY is the
+ * binary symmetric channel on X errors of the paper's experiments (Section IV):
+ * each qubit suffers an X error with probability p, never Z.
+ * MBBP_EINVAL for any other value; a null ctx is MBBP_EINVAL. */
+enum { MBBP_NOISE_DEPOLARIZING = 0, MBBP_NOISE_X_ONLY = 1 };
+mbbp_status mbbp_set_noise(mbbp_ctx *ctx, int32_t model);
+
+/* Counter-based code-capacity noise: qubit q of shot s uses the 32-bit half (q%2)
+ * of word (q%8)/2 of Philox4x64-10(counter = (s, q/8, 0, 0), key = (seed, 0))
+ * [Salmon et al. SC'11].  Depolarizing (X, Y, Z each with probability p/3):
  * u < t1 -> X, u < t2 -> Y, u < t3 -> Z with t_k = floor(k * (p/3) * 2^32) in
- * double precision.  Shots are indexed shot0 .. shot0 + shots - 1.
+ * double precision.  X only: X iff u < floor(p * 2^32), e_Z = 0.  Shots are
+ * indexed shot0 .. shot0 + shots - 1.
  * err_x, err_z device [shots][ceil(n/64)]; syn_x = H_Z e_X, syn_z = H_X e_Z as above.
  * 0 <= p <= 1, 0 < shots <= max_batch. */
 mbbp_status mbbp_sample(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
@@ -185,7 +194,8 @@ enum {
  * captured on first use for this `shots` (direct launches while BP timing is
  * enabled, see mbbp_set_timing, or with mbbp_set_graph(ctx, 0)).  counters: device int64
  * [MBBP_NUM_COUNTERS], ACCUMULATED into (the caller zeroes it).  Uniform
- * priors log((1 - 2p/3) / (2p/3)) for both parts. */
+ * priors log((1 - q) / q) for both parts, q = 2p/3 under depolarizing noise and
+ * q = p under X-only noise (mbbp_set_noise). */
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
                      int64_t *counters, void *hip_stream);
 

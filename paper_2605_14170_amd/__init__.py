@@ -22,6 +22,7 @@ from ._lib import MbbpError, NUM_COUNTERS  # noqa: F401
 FLOODING, LAYERED = 0, 1
 NMS, SPA, WEIGHTED = 0, 1, 2
 MIN_WEIGHT, FWS = 0, 1
+DEPOLARIZING, X_ONLY = 0, 1  # noise models (mbbp_set_noise)
 PART_X, PART_Z = 0, 1
 
 CNT_FAIL, CNT_FAIL_X, CNT_FAIL_Z, CNT_SUM_KMAX, CNT_SUM_K, CNT_EDGE_UPDATES, CNT_NOCONV, CNT_TIES = range(8)
@@ -260,6 +261,10 @@ class Decoder:
                                             ctypes.byref(cfg)), "mbbp_autotune")
         return dict(lanes_per_instance=cfg.lanes_per_instance, waves_per_block=cfg.waves_per_block,
                     chunk=cfg.chunk, blocks=cfg.blocks)
+
+    def set_noise(self, model: int) -> None:
+        """Noise model of sample(), run() and autotune(): DEPOLARIZING or X_ONLY."""
+        _lib.check(_lib.lib().mbbp_set_noise(self._ctx, int(model)), "mbbp_set_noise")
 
     def set_graph(self, enable: bool) -> None:
         _lib.check(_lib.lib().mbbp_set_graph(self._ctx, 1 if enable else 0), "mbbp_set_graph")

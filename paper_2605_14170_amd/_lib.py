@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "mbbp_get_config": ([P, i32, ctypes.POINTER(LaunchConfig)], i32),
             "mbbp_autotune": ([P, i32, u64, dbl, i64, ctypes.POINTER(LaunchConfig)], i32),
             "mbbp_set_graph": ([P, i32], i32),
+            "mbbp_set_noise": ([P, i32], i32),
             "mbbp_bp_time": ([P, P, P, i32], i32),
             "mbbp_set_weights": ([P, P, P], i32),
             "mbbp_wbp_ckpt_floats": ([P, i32, i64, i32, P], i32),
@@ -106,4 +107,5 @@ EXPORTED = ["mbbp_params_default", "mbbp_create", "mbbp_destroy", "mbbp_decode",
             "mbbp_decode_detail", "mbbp_sample", "mbbp_failures", "mbbp_run", "mbbp_subtrees",
             "mbbp_build_bases", "mbbp_logicals", "mbbp_edge_counts", "mbbp_last_error", "mbbp_set_timing",
             "mbbp_bp_time", "mbbp_set_config", "mbbp_get_config", "mbbp_autotune", "mbbp_set_graph",
-            "mbbp_set_weights", "mbbp_wbp_ckpt_floats", "mbbp_wbp_forward", "mbbp_wbp_backward"]
+            "mbbp_set_weights", "mbbp_wbp_ckpt_floats", "mbbp_wbp_forward", "mbbp_wbp_backward",
+            "mbbp_set_noise"]

@@ -425,6 +425,7 @@ struct RunGraph {
 struct mbbp_ctx {
     int device = 0;
     int n = 0, T = 0, schedule = 0;
+    int noise = MBBP_NOISE_DEPOLARIZING;  // noise model of mbbp_sample / mbbp_run / mbbp_autotune
     mbbp_params params{};
     HostPart hp[2];  // [0] = part X (H_Z), [1] = part Z (H_X)
     std::vector<Row> HX, HZ;
@@ -983,8 +984,28 @@ mbbp_status mbbp_decode_batched(mbbp_ctx *ctx, int64_t shots, const uint64_t *sy
                          conv_z, basis_x, basis_z, hip_stream, true);
 }
 
-static void thresholds(double p, uint64_t t[3]) {
+// Sampler thresholds: u < t1 -> X, u < t2 -> Y, u < t3 -> Z.  Depolarizing:
+// t_k = floor(k (p/3) 2^32).  X errors only: t1 = t2 = t3 = floor(p 2^32), so a
+// qubit takes X iff u < floor(p 2^32) and never Y or Z.
+static void thresholds(double p, int noise, uint64_t t[3]) {
+    if (noise == MBBP_NOISE_X_ONLY) {
+        t[0] = t[1] = t[2] = (uint64_t)std::floor(p * 4294967296.0);
+        return;
+    }
     for (int k = 1; k <= 3; ++k) t[k - 1] = (uint64_t)std::floor((double)k * (p / 3.0) * 4294967296.0);
+}
+
+// Flip probability of each part under the context's noise model (the uniform
+// prior log((1 - q) / q) of mbbp_run): 2p/3 depolarizing, p for X errors only.
+static double part_flip_prob(const mbbp_ctx *ctx, double p) {
+    return ctx->noise == MBBP_NOISE_X_ONLY ? p : 2.0 * p / 3.0;
+}
+
+mbbp_status mbbp_set_noise(mbbp_ctx *ctx, int32_t model) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (model != MBBP_NOISE_DEPOLARIZING && model != MBBP_NOISE_X_ONLY) return fail(MBBP_EINVAL, "unknown noise model");
+    ctx->noise = model;
+    return MBBP_OK;
 }
 
 mbbp_status mbbp_sample(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, uint64_t *err_x,
@@ -999,7 +1020,7 @@ mbbp_status mbbp_sample(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, i
     a.n = ctx->n;
     a.seed = seed;
     uint64_t t[3];
-    thresholds(p, t);
+    thresholds(p, ctx->noise, t);
     a.t1 = t[0]; a.t2 = t[1]; a.t3 = t[2];
     a.shot0 = shot0;
     a.shots = shots;
@@ -1110,12 +1131,12 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     mbbp_status st = ensure_run_workspace(ctx);
     if (st != MBBP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const double q = 2.0 * p / 3.0;
+    const double q = part_flip_prob(ctx, p);
     mbbp::RunPrepArgs prep{};
     prep.d.seed = seed;
     prep.d.shot0 = shot0;
     uint64_t t[3];
-    thresholds(p, t);
+    thresholds(p, ctx->noise, t);
     prep.d.t1 = t[0]; prep.d.t2 = t[1]; prep.d.t3 = t[2];
     prep.d.counters = counters;
     prep.desc = ctx->w_desc;
@@ -1202,7 +1223,7 @@ mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, 
     if ((st = mbbp_sample(ctx, seed, p, 0, shots, ctx->w_err[0], ctx->w_err[1], ctx->w_syn[0], ctx->w_syn[1], s)) !=
         MBBP_OK)
         return st;
-    const double q = 2.0 * p / 3.0;
+    const double q = part_flip_prob(ctx, p);
     std::vector<float> mu(ctx->n, (float)std::log((1.0 - q) / q));
     for (int pt = 0; pt < 2; ++pt)
         MBBP_HIP(hipMemcpyAsync(ctx->w_prior[pt], mu.data(), mu.size() * 4, hipMemcpyHostToDevice, s));

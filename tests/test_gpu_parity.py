@@ -74,6 +74,26 @@ def test_sampler_bit_exact(pk, key, p, shot0, shots):
     dec.close()
 
 
+@pytest.mark.parametrize("key,p,shot0,shots", [("bb144_L16_T50", 0.07, 999, 513), ("bb72_L4_T20", 0.5, 0, 64)])
+def test_sampler_x_only_bit_exact(pk, key, p, shot0, shots):
+    """X-only noise (mbbp_set_noise): errors and syndromes equal the oracle's."""
+    wl = WORKLOADS[key]
+    code = wl.code()
+    bases = (np.zeros(2, np.int32), np.zeros(0, np.int32))
+    say(f"sampler x-only {key} p={p} shot0={shot0} shots={shots}")
+    dec = pk.Decoder(code.hx, code.hz, bases, bases, 1, max_batch=shots)
+    dec.set_noise(pk.X_ONLY)
+    ex, ez, sx, sz = dec.sample(wl.seed, p, shot0, shots)
+    torch.cuda.synchronize()
+    oex, oez, osx, osz = oracle.sample(code.hx, code.hz, wl.seed, p, shot0, shots, oracle.BSC_X)
+    np.testing.assert_array_equal(words(ex), oex)
+    np.testing.assert_array_equal(words(ez), oez)
+    np.testing.assert_array_equal(words(sx), osx)
+    np.testing.assert_array_equal(words(sz), osz)
+    assert not oez.any()
+    dec.close()
+
+
 # ------------------------------------------------------------------------ NMS flooding, bit-exact vs FP32 oracle
 
 def _detail_vs_oracle(pk, dec, code, bx, bz, wl, p, shot0, shots, precision, fixed_T=False):
@@ -288,14 +308,39 @@ def test_run_counters_match_oracle(pk):
     shots, p, shot0 = 1200, 0.08, 99
     dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
     say(f"mbbp_run counters bb144 p={p} shots={shots}")
+    _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots)
+    dec.close()
+
+
+def test_run_x_only_layered_matches_oracle(pk):
+    """The paper's experimental conditions (Section IV): X errors only (binary
+    symmetric channel, prior log((1 - p) / p)), layered schedule, T = 100; mbbp_run's
+    counters equal the FP32 oracle's exactly (part Z sees no errors)."""
+    wl = WORKLOADS["bb144_L16_T50"]
+    code = wl.code()
+    shots, p, shot0, T = 500, 0.07, 4321, 100
+    dec, bx, bz = make_decoder(pk, code, wl, T=T, max_batch=shots, schedule=pk.LAYERED)
+    dec.set_noise(pk.X_ONLY)
+    say(f"mbbp_run x-only layered bb144 p={p} shots={shots} T={T}")
+    cnt = _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots, T=T, schedule=oracle.LAYERED,
+                         noise=oracle.BSC_X)
+    assert cnt[pk.CNT_FAIL_Z] == 0 and cnt[pk.CNT_FAIL] == cnt[pk.CNT_FAIL_X]
+    dec.close()
+
+
+def _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots, T=None, schedule=None, noise=None):
+    T = wl.T if T is None else T
+    schedule = oracle.FLOODING if schedule is None else schedule
+    noise = oracle.DEPOLARIZING if noise is None else noise
     cnt = dec.run(wl.seed, p, shot0, shots).cpu().numpy()
-    ex, ez, sx, sz = oracle.sample(code.hx, code.hz, wl.seed, p, shot0, shots)
-    mu = f32(oracle.prior_llr(p))
+    ex, ez, sx, sz = oracle.sample(code.hx, code.hz, wl.seed, p, shot0, shots, noise)
+    mu = f32(oracle.prior_llr(p, noise))
     fails = np.zeros((2, shots), bool)
     kmax = np.zeros(shots, np.int64)
     sum_k = edges = noconv = 0
     for part, h, (bp, rows), syn, err, stab in ((0, code.hz, bz, sx, ex, code.hx), (1, code.hx, bx, sz, ez, code.hz)):
-        ref = oracle.decode(h, bp, rows, syn, np.full(code.n, mu), wl.T, alpha=wl.alpha, precision="f32")
+        ref = oracle.decode(h, bp, rows, syn, np.full(code.n, mu), T, schedule=schedule, alpha=wl.alpha,
+                            precision="f32")
         fails[part] = oracle.failures(stab, err, ref.corr)
         kmax = np.maximum(kmax, ref.K.max(axis=1))
         sum_k += int(ref.K.sum())
@@ -308,7 +353,7 @@ def test_run_counters_match_oracle(pk):
     for k, v in expect.items():
         assert int(cnt[k]) == v, (k, int(cnt[k]), v)
     say(f"  counters {cnt.tolist()}")
-    dec.close()
+    return cnt
 
 
 @pytest.mark.parametrize("factory", [codes.steane7, codes.surface13, codes.toric18])
