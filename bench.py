@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--ler-ps", default="0.03,0.04,0.05,0.06,0.07,0.08", help="--paper-ler: error rates")
     ap.add_argument("--ler-failures", type=int, default=100, help="--paper-ler: failures per point")
     ap.add_argument("--ler-max-shots", type=int, default=50_000_000, help="--paper-ler: shot cap per point")
+    ap.add_argument("--ler-bases", choices=["workload", "tree", "random"], default="workload",
+                    help="--paper-ler: the workload's bases, or per partition (the maximal subtrees of one "
+                         "root order, Algorithm 2) its subtree rows (tree) or as many random rows (random)")
+    ap.add_argument("--ler-partitions", type=int, default=1, help="--paper-ler with tree/random: partitions")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -154,9 +158,45 @@ def paper_ler_main(args, wl, code):
     batch = args.shots or 1_000_000
     torch.cuda.set_device(0)
     from workloads.perms import check_permutations
-    perms = lambda h: check_permutations(h.shape[0], max(wl.L, 8), wl.perm_seed)  # noqa: E731
-    bx = pk.build_bases(code.hx, wl.basis_mode, wl.L, perms(code.hx))
-    bz = pk.build_bases(code.hz, wl.basis_mode, wl.L, perms(code.hz))
+    if args.ler_bases == "workload":
+        perms = lambda h: check_permutations(h.shape[0], max(wl.L, 8), wl.perm_seed)  # noqa: E731
+        cases = [(None, pk.build_bases(code.hx, wl.basis_mode, wl.L, perms(code.hx)),
+                  pk.build_bases(code.hz, wl.basis_mode, wl.L, perms(code.hz)))]
+    else:
+        # part X (the only one with errors under X-only noise) decodes on the partition
+        # of H_Z; part Z takes as many representations of H_X's partition (cycled), as
+        # the library runs the same number for both parts
+        cases = []
+        for k in range(args.ler_partitions):
+            bz = partition_bases(pk, code.hz, k, wl.perm_seed, args.ler_bases)
+            bx = partition_bases(pk, code.hx, k, wl.perm_seed, args.ler_bases, count=len(bz[0]) - 1)
+            cases.append((k, bx, bz))
+    for part_k, bx, bz in cases:
+        paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k)
+
+
+def partition_bases(pk, h, k, seed, mode, count=None):
+    """Bases of partition k: the maximal subtrees of root order pi_k (Algorithm 2,
+    pi_0 the identity), one representation [H; H_t] per subtree t with H_t its rows in
+    acceptance order (tree), or |H_t| distinct rows of H drawn at random (random,
+    the matched random augmentation of the paper's Table II)."""
+    from workloads.perms import check_permutations
+    m = h.shape[0]
+    perm = check_permutations(m, k + 1, seed)[k]
+    cs, order, ns = pk.subtrees(h, perm)
+    rng = np.random.Generator(np.random.PCG64([int(seed), 7919, int(k)]))
+    subs = [[int(c) for c in order if cs[c] == t] for t in range(1, ns + 1)]
+    bp, rows = [0], []
+    for i in range(ns if count is None else count):
+        sub = subs[i % ns]
+        rows += sub if mode == "tree" else [int(x) for x in rng.choice(m, len(sub), replace=False)]
+        bp.append(len(rows))
+    return np.asarray(bp, np.int32), np.asarray(rows, np.int32)
+
+
+def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
+    import torch
+    L = len(bx[0]) - 1
     dec = pk.Decoder(code.hx, code.hz, bx, bz, 100, schedule=pk.LAYERED, alpha=0.875, select=pk.FWS,
                      max_batch=batch)
     dec.set_noise(pk.X_ONLY)
@@ -174,12 +214,13 @@ def paper_ler_main(args, wl, code):
         cc = c.cpu().numpy()
         f = int(cc[pk.CNT_FAIL])
         lo, hi = wilson(f, shots)
+        bases = wl.basis_mode if part_k is None else f"{args.ler_bases} partition {part_k}"
         print(json.dumps(dict(workload=wl.key, code=wl.key.split("_")[0], noise="x_only", schedule="layered",
-                              T=100, alpha=0.875, decision="FWS", L=wl.L, basis_mode=wl.basis_mode, p=p,
+                              T=100, alpha=0.875, decision="FWS", L=L, bases=bases, p=p,
                               shots=shots, failures=f, ler=f / shots, ler_95=[lo, hi],
                               mean_kmax=float(cc[pk.CNT_SUM_KMAX]) / shots,
                               # part Z sees no errors (K = 0 there): mean iterations of part X
-                              mean_k=float(cc[pk.CNT_SUM_K]) / (wl.L * shots),
+                              mean_k=float(cc[pk.CNT_SUM_K]) / (L * shots),
                               noconv=int(cc[pk.CNT_NOCONV]), seconds=round(dt, 3))), flush=True)
     dec.close()
 
