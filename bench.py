@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 # Algorithmic VALU lane-operations per edge-message update of normalized min-sum
 # (two-minimum tracking 2, sign parity 1, minimum test and select 2, sign apply 1,
 # per-check scaling and clamp ~0.7, posterior and message sums 2, syndrome parity 1,
-# decision ~0.3); see the design doc.
+# decision ~0.3).
 OPS_PER_EDGE_UPDATE = 10.0
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed 32-bit VALU lane-ops)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -338,9 +338,8 @@ def weighted_main(args, wl, code):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              f"design (shot sharding, one all-reduce of counters) is described in DESIGN.md "
-              f"and not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); a multi-GPU run "
+              f"(shot sharding with one all-reduce of the counters) is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 
