@@ -129,3 +129,12 @@ def test_last_error_is_thread_local_text():
     with pytest.raises(pk.MbbpError):
         pk.subtrees(codes.bb72().hx, np.zeros(36, np.int32))
     assert b"permutation" in lib.mbbp_last_error()
+
+
+def test_set_noise_validates_arguments():
+    """mbbp_set_noise: a null context and an unknown model are MBBP_EINVAL (host
+    checks only, no device call)."""
+    lib = _lib.lib()
+    assert lib.mbbp_set_noise(None, 0) == -1
+    assert b"null ctx" in lib.mbbp_last_error()
+    assert pk.DEPOLARIZING == 0 and pk.X_ONLY == 1 and oracle.BSC_X == pk.X_ONLY
