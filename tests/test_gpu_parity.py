@@ -223,6 +223,46 @@ def test_decode_select_failures_bit_exact(pk):
     dec.close()
 
 
+def test_full_size_sampled_shots_bit_exact(pk):
+    """The timed configuration at full size: [[144,12,12]], L = 16, T = 50, 10^6 shots
+    at the heaviest error rate (p = 0.08) through the persistent batched form with
+    the default launch shape.  Sampled shots (the first, the last and 240 spread
+    over the range) are recomputed one by one by the FP32 oracle from its own
+    sampler: corrections, chosen representation, convergence masks and failure
+    flags equal bit for bit."""
+    wl = WORKLOADS["bb144_L16_T50"]
+    code = wl.code()
+    shots, p, shot0 = wl.shots, 0.08, 3 * wl.shots
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
+    say(f"full size bb144 p={p} shots={shots} (sampled shots vs oracle)")
+    ex, ez, sx, sz = dec.sample(wl.seed, p, shot0, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    out = dec.decode_batched(sx, sz, prior, prior)
+    fail = dec.failures(ex, ez, out["corr_x"], out["corr_z"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    pick = np.unique(np.concatenate([np.arange(8), np.arange(shots - 8, shots),
+                                     rng.choice(shots, 240, replace=False)]))
+    samp = [oracle.sample(code.hx, code.hz, wl.seed, p, shot0 + int(i), 1) for i in pick]
+    oex, oez, osx, osz = (np.concatenate([t[k] for t in samp]) for k in range(4))
+    np.testing.assert_array_equal(words(sx)[pick], osx)
+    np.testing.assert_array_equal(words(sz)[pick], osz)
+    fail_ref = np.zeros(len(pick), np.uint8)
+    for part, h, (bp, rows), syn, err, stab in ((0, code.hz, bz, osx, oex, code.hx),
+                                                 (1, code.hx, bx, osz, oez, code.hz)):
+        ref = oracle.decode(h, bp, rows, syn, np.full(code.n, mu), wl.T, alpha=wl.alpha, precision="f32")
+        tag = "x" if part == 0 else "z"
+        np.testing.assert_array_equal(words(out[f"corr_{tag}"])[pick], ref.corr)
+        np.testing.assert_array_equal(out[f"basis_{tag}"].cpu().numpy()[pick], ref.chosen)
+        mask = (ref.conv.astype(np.uint64) << np.arange(wl.L, dtype=np.uint64)).sum(axis=1).astype(np.uint64)
+        np.testing.assert_array_equal(words(out[f"conv_{tag}"])[pick], mask)
+        fail_ref |= oracle.failures(stab, err, ref.corr).astype(np.uint8) << part
+    np.testing.assert_array_equal(fail.cpu().numpy()[pick], fail_ref)
+    say(f"  {len(pick)} sampled shots equal; LER over all {shots}: {float((fail.cpu().numpy() != 0).mean()):.4f}")
+    dec.close()
+
+
 def test_batched_bit_identical_to_plain(pk):
     wl = WORKLOADS["bb144_L16_T50"]
     code = wl.code()
