@@ -223,18 +223,21 @@ def test_decode_select_failures_bit_exact(pk):
     dec.close()
 
 
-def test_full_size_sampled_shots_bit_exact(pk):
-    """The timed configuration at full size: [[144,12,12]], L = 16, T = 50, 10^6 shots
-    at the heaviest error rate (p = 0.08) through the persistent batched form with
-    the default launch shape.  Sampled shots (the first, the last and 240 spread
-    over the range) are recomputed one by one by the FP32 oracle from its own
-    sampler: corrections, chosen representation, convergence masks and failure
-    flags equal bit for bit."""
-    wl = WORKLOADS["bb144_L16_T50"]
+@pytest.mark.parametrize("key,p,spread", [("bb144_L16_T50", 0.08, 240), ("bb288_L32_T100", 0.03, 112),
+                                          ("qc882_L64_T100", 0.03, 48)])
+def test_full_size_sampled_shots_bit_exact(pk, key, p, spread):
+    """The workloads at full size through the persistent batched form with the
+    default launch shape: [[144,12,12]] L = 16, T = 50, 10^6 shots at the heaviest
+    error rate; [[288,12,18]] L = 32, T = 100, 10^7 shots; the n = 882 stand-in
+    L = 64, T = 100, 10^6 shots at the heaviest rate.  Sampled shots (the first 8,
+    the last 8 and some spread over the range) are recomputed one by one by the
+    FP32 oracle from its own sampler: corrections, chosen representation,
+    convergence masks and failure flags equal bit for bit."""
+    wl = WORKLOADS[key]
     code = wl.code()
-    shots, p, shot0 = wl.shots, 0.08, 3 * wl.shots
+    shots, shot0 = wl.shots, 3 * wl.shots
     dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
-    say(f"full size bb144 p={p} shots={shots} (sampled shots vs oracle)")
+    say(f"full size {key} p={p} shots={shots} (sampled shots vs oracle)")
     ex, ez, sx, sz = dec.sample(wl.seed, p, shot0, shots)
     mu = f32(oracle.prior_llr(p))
     prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
@@ -243,7 +246,7 @@ def test_full_size_sampled_shots_bit_exact(pk):
     torch.cuda.synchronize()
     rng = np.random.default_rng(8)
     pick = np.unique(np.concatenate([np.arange(8), np.arange(shots - 8, shots),
-                                     rng.choice(shots, 240, replace=False)]))
+                                     rng.choice(shots, spread, replace=False)]))
     samp = [oracle.sample(code.hx, code.hz, wl.seed, p, shot0 + int(i), 1) for i in pick]
     oex, oez, osx, osz = (np.concatenate([t[k] for t in samp]) for k in range(4))
     np.testing.assert_array_equal(words(sx)[pick], osx)
@@ -259,7 +262,7 @@ def test_full_size_sampled_shots_bit_exact(pk):
         np.testing.assert_array_equal(words(out[f"conv_{tag}"])[pick], mask)
         fail_ref |= oracle.failures(stab, err, ref.corr).astype(np.uint8) << part
     np.testing.assert_array_equal(fail.cpu().numpy()[pick], fail_ref)
-    say(f"  {len(pick)} sampled shots equal; LER over all {shots}: {float((fail.cpu().numpy() != 0).mean()):.4f}")
+    say(f"  {len(pick)} sampled shots equal; LER over all {shots}: {float((fail.cpu().numpy() != 0).mean()):.3e}")
     dec.close()
 
 
