@@ -266,6 +266,65 @@ def test_full_size_sampled_shots_bit_exact(pk, key, p, spread):
     dec.close()
 
 
+def test_degenerate_inputs(pk):
+    """Edge cases of the method and of the boundary: zero syndromes (p = 0: every
+    representation converges at t = 0 to the all-zero decision, the least-weight
+    rule picks representation 0), T = 0 (only the t = 0 halting test: bit-exact
+    against the oracle, unconverged shots decide all-zero), a single shot, and
+    rejected sizes (0 shots, more than max_batch, p = 0 for the whole path) that
+    fail with MBBP_EINVAL before any launch."""
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    mu = f32(oracle.prior_llr(0.05))
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=64)
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    say("degenerate inputs: zero syndromes, one shot, rejected sizes")
+    ex, ez, sx, sz = dec.sample(wl.seed, 0.0, 0, 64)
+    cand, kstat, _ = dec.decode_detail(0, sx, prior)
+    out = dec.decode_batched(sx, sz, prior, prior)
+    torch.cuda.synchronize()
+    assert not words(ex).any() and not words(sx).any() and not words(sz).any()
+    assert (kstat.cpu().numpy().view(np.uint16) == 0x8000).all()   # converged at K = 0
+    assert not words(cand).any()
+    for tag in ("x", "z"):
+        assert not words(out[f"corr_{tag}"]).any()
+        assert (words(out[f"conv_{tag}"]) == (1 << wl.L) - 1).all()
+        assert (out[f"basis_{tag}"].cpu().numpy() == 0).all()
+    # one shot, bit-exact
+    _, _, sx1, _ = dec.sample(wl.seed, 0.05, 12345, 1)
+    cand1, kstat1, _ = dec.decode_detail(0, sx1, prior)
+    torch.cuda.synchronize()
+    _, _, osx1, _ = oracle.sample(code.hx, code.hz, wl.seed, 0.05, 12345, 1)
+    ref1 = oracle.decode(code.hz, *bz, osx1, np.full(code.n, mu), wl.T, alpha=wl.alpha, precision="f32")
+    np.testing.assert_array_equal(words(cand1), ref1.cand)
+    np.testing.assert_array_equal(kstat1.cpu().numpy().view(np.uint16) & 0x7FFF, ref1.K)
+    for call in (lambda: dec.sample(1, 0.05, 0, 0), lambda: dec.sample(1, 0.05, 0, 65),
+                 lambda: dec.run(1, 0.05, 0, 65), lambda: dec.run(1, 0.0, 0, 10)):
+        with pytest.raises(pk.MbbpError) as ei:
+            call()
+        assert ei.value.status == -1
+    dec.close()
+    # T = 0
+    shots = 300
+    dec0, bx, bz = make_decoder(pk, code, wl, T=0, max_batch=shots)
+    _, _, sx, sz = dec0.sample(wl.seed, 0.05, 0, shots)
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        cand, kstat, llr = dec0.decode_detail(part, syn, prior, want_llr=True)
+        out = dec0.decode(sx, sz, prior, prior)
+        torch.cuda.synchronize()
+        ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), 0, alpha=wl.alpha, want_llr=True,
+                            precision="f32")
+        ks = kstat.cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
+        np.testing.assert_array_equal((ks >> 15).astype(bool), ref.conv)
+        np.testing.assert_array_equal(words(cand), ref.cand)
+        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+        tag = "x" if part == 0 else "z"
+        np.testing.assert_array_equal(words(out[f"corr_{tag}"]), ref.corr)
+        np.testing.assert_array_equal(out[f"basis_{tag}"].cpu().numpy(), ref.chosen)
+    dec0.close()
+
+
 def test_batched_bit_identical_to_plain(pk):
     wl = WORKLOADS["bb144_L16_T50"]
     code = wl.code()
