@@ -325,6 +325,44 @@ def test_degenerate_inputs(pk):
     dec0.close()
 
 
+@pytest.mark.parametrize("key,p,shots", [("bb144_L16_T50", 0.08, 3000), ("bb72_L4_T20", 0.1, 4000)])
+def test_fws_decision_bit_exact(pk, key, p, shots):
+    """The paper's FWS decision (Section III-B: frequency of a candidate in the list
+    over its weight + 1) in the plain and batched paths: corrections, chosen
+    representation and failure flags equal the FP32 oracle's, and FWS picks
+    differently from least weight on some shots."""
+    wl = WORKLOADS[key]
+    code = wl.code()
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots, select=pk.FWS)
+    lw, _, _ = make_decoder(pk, code, wl, max_batch=shots)
+    say(f"FWS decision {key} p={p} shots={shots}")
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 4242, shots)
+    mu = f32(oracle.prior_llr(p))
+    prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
+    out = dec.decode(sx, sz, prior, prior)
+    outb = dec.decode_batched(sx, sz, prior, prior)
+    outl = lw.decode(sx, sz, prior, prior)
+    fail = dec.failures(ex, ez, out["corr_x"], out["corr_z"])
+    torch.cuda.synchronize()
+    differ = 0
+    fail_ref = np.zeros(shots, np.uint8)
+    for part, h, (bp, rows), syn, err, stab in ((0, code.hz, bz, sx, ex, code.hx),
+                                                 (1, code.hx, bx, sz, ez, code.hz)):
+        ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), wl.T, alpha=wl.alpha,
+                            select_rule=oracle.FWS, precision="f32")
+        tag = "x" if part == 0 else "z"
+        for o in (out, outb):
+            np.testing.assert_array_equal(words(o[f"corr_{tag}"]), ref.corr)
+            np.testing.assert_array_equal(o[f"basis_{tag}"].cpu().numpy(), ref.chosen)
+        differ += int((outl[f"basis_{tag}"].cpu().numpy() != ref.chosen).sum())
+        fail_ref |= oracle.failures(stab, words(err), ref.corr).astype(np.uint8) << part
+    np.testing.assert_array_equal(fail.cpu().numpy(), fail_ref)
+    assert differ > 0
+    say(f"  FWS and least weight choose differently on {differ} (shot, part) pairs")
+    dec.close()
+    lw.close()
+
+
 def test_batched_bit_identical_to_plain(pk):
     wl = WORKLOADS["bb144_L16_T50"]
     code = wl.code()
@@ -421,16 +459,17 @@ def test_run_x_only_layered_matches_oracle(pk):
     wl = WORKLOADS["bb144_L16_T50"]
     code = wl.code()
     shots, p, shot0, T = 500, 0.07, 4321, 100
-    dec, bx, bz = make_decoder(pk, code, wl, T=T, max_batch=shots, schedule=pk.LAYERED)
+    dec, bx, bz = make_decoder(pk, code, wl, T=T, max_batch=shots, schedule=pk.LAYERED, select=pk.FWS)
     dec.set_noise(pk.X_ONLY)
-    say(f"mbbp_run x-only layered bb144 p={p} shots={shots} T={T}")
+    say(f"mbbp_run x-only layered FWS bb144 p={p} shots={shots} T={T}")
     cnt = _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots, T=T, schedule=oracle.LAYERED,
-                         noise=oracle.BSC_X)
+                         noise=oracle.BSC_X, select_rule=oracle.FWS)
     assert cnt[pk.CNT_FAIL_Z] == 0 and cnt[pk.CNT_FAIL] == cnt[pk.CNT_FAIL_X]
     dec.close()
 
 
-def _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots, T=None, schedule=None, noise=None):
+def _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots, T=None, schedule=None, noise=None,
+                   select_rule=None):
     T = wl.T if T is None else T
     schedule = oracle.FLOODING if schedule is None else schedule
     noise = oracle.DEPOLARIZING if noise is None else noise
@@ -442,6 +481,7 @@ def _run_vs_oracle(pk, dec, code, wl, bx, bz, p, shot0, shots, T=None, schedule=
     sum_k = edges = noconv = 0
     for part, h, (bp, rows), syn, err, stab in ((0, code.hz, bz, sx, ex, code.hx), (1, code.hx, bx, sz, ez, code.hz)):
         ref = oracle.decode(h, bp, rows, syn, np.full(code.n, mu), T, schedule=schedule, alpha=wl.alpha,
+                            select_rule=oracle.MIN_WEIGHT if select_rule is None else select_rule,
                             precision="f32")
         fails[part] = oracle.failures(stab, err, ref.corr)
         kmax = np.maximum(kmax, ref.K.max(axis=1))
