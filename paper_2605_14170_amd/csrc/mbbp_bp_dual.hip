@@ -301,9 +301,8 @@ void bp_dual_kernel(BPArgs a) {
                                 if (v * 32 + half < n) llr[inst * n + (vid[v] & 0xffffu)] = Pl[v];
                         }
                     }
-                    // bit-packed hard decisions via the instance's staging words
-                    if (lane < 2 * W) lds_ptr_u32(stage_addr[c])[lane] = 0u;
-                    wave_sync();
+                    // bit-packed hard decisions via the instance's staging words (zero:
+                    // cleared with the region, and again after every read below)
                     if (comp == c) {
 #pragma unroll
                         for (int v = 0; v < PV2; ++v)
@@ -315,7 +314,10 @@ void bp_dual_kernel(BPArgs a) {
                     wave_sync();
                     // representation-major: a work item's records are contiguous
                     const size_t oi = a.cand_rm ? (size_t)l * a.shots + shot[c] : inst;
-                    if (lane < W) cand[oi * W + lane] = lds_ptr_u64(stage_addr[c])[lane];
+                    if (lane < W) {
+                        cand[oi * W + lane] = lds_ptr_u64(stage_addr[c])[lane];
+                        lds_ptr_u64(stage_addr[c])[lane] = 0ull;
+                    }
                     if (lane == 0) kstat[oi] = (uint16_t)(K | (conv ? 0x8000 : 0));
                     it[c] = 0;
                     if (next < ip.end) {
