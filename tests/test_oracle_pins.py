@@ -413,6 +413,192 @@ def test_zero_syndrome_stops_at_iteration_zero():
     assert (res.K == 0).all() and res.conv.all() and (res.corr == 0).all() and (res.chosen == 0).all()
 
 
+def _chain():
+    """Two weight-2 checks on three variables: c0 = {v0, v1}, c1 = {v1, v2}."""
+    return np.array([[1, 1, 0], [0, 1, 1]], np.uint8)
+
+
+@pytest.mark.parametrize("schedule", [oracle.FLOODING, oracle.LAYERED])
+def test_halting_iteration_two_on_a_chain(schedule):
+    """Halting rule of Section II-B (stop at the first t whose hard decision meets
+    the syndrome).  Chain c0 = {v0, v1}, c1 = {v1, v2}, s = (0, 1), mu = (2, 1, 4),
+    alpha = 1, worked by hand.  Flooding:
+      t=1: q = mu; r(c0->v0) = 1, r(c0->v1) = 2, r(c1->v1) = -4, r(c1->v2) = -1
+           P = (3, -1, 3), e = (0, 1, 0): c0 has parity 1 != 0, not met;
+      t=2: q(v1->c0) = 1 - 4 = -3, q(v1->c1) = 1 + 2 = 3
+           r(c0->v0) = -3, r(c0->v1) = 2, r(c1->v1) = -4, r(c1->v2) = -3
+           P = (-1, -1, 1), e = (1, 1, 0): parities (0, 1) = s, met: K = 2.
+    Serial (rows in order, r = 0 before the first sweep):
+      t=1: c0 sees q(v1) = 1 + 0: r(c0->v0) = 1, r(c0->v1) = 2; c1 sees
+           q(v1) = 1 + 2 = 3: r(c1->v1) = -4, r(c1->v2) = -3; P = (3, -1, 1),
+           e = (0, 1, 0), not met;
+      t=2: c0 sees q(v1) = -3: r(c0->v0) = -3, r(c0->v1) = 2; c1 as before;
+           P = (-1, -1, 1), met: K = 2."""
+    h = _chain()
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    syn = oracle.pack(np.array([[0, 1]], np.uint8))
+    res = oracle.decode(h, bp, rows, syn, np.array([2.0, 1.0, 4.0]), T=10, schedule=schedule, alpha=1.0,
+                        want_llr=True)
+    assert int(res.K[0, 0]) == 2 and bool(res.conv[0, 0])
+    np.testing.assert_array_equal(res.llr[0, 0], [-1.0, -1.0, 1.0])
+    np.testing.assert_array_equal(oracle.unpack(res.corr, 3)[0], [1, 1, 0])
+    assert int(res.chosen[0]) == 0
+    # one iteration short of K: the same decoder with T = 1 does not converge and
+    # reports the t = 1 state
+    r1 = oracle.decode(h, bp, rows, syn, np.array([2.0, 1.0, 4.0]), T=1, schedule=schedule, alpha=1.0,
+                       want_llr=True)
+    assert int(r1.K[0, 0]) == 1 and not bool(r1.conv[0, 0]) and int(r1.chosen[0]) == -1
+    expect_t1 = [3.0, -1.0, 3.0] if schedule == oracle.FLOODING else [3.0, -1.0, 1.0]
+    np.testing.assert_array_equal(r1.llr[0, 0], expect_t1)
+    assert not r1.corr.any()
+
+
+def test_halting_iteration_separates_the_schedules():
+    """The chain with its rows swapped, c0 = {v1, v2}, c1 = {v0, v1}, s = (1, 0),
+    mu = (2, 1, 4), alpha = 1.  Serial, t=1: c0 sees q = (1, 4): r(c0->v1) = -4,
+    r(c0->v2) = -1; c1 sees q(v0) = 2, q(v1) = 1 - 4 = -3: r(c1->v0) = -3,
+    r(c1->v1) = 2; P = (-1, -1, 3), e = (1, 1, 0) meets s: K = 1.  Flooding needs
+    the second iteration as above (the same graph): K = 2."""
+    h = _chain()[::-1].copy()
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    syn = oracle.pack(np.array([[1, 0]], np.uint8))
+    mu = np.array([2.0, 1.0, 4.0])
+    se = oracle.decode(h, bp, rows, syn, mu, T=10, schedule=oracle.LAYERED, alpha=1.0, want_llr=True)
+    fl = oracle.decode(h, bp, rows, syn, mu, T=10, schedule=oracle.FLOODING, alpha=1.0, want_llr=True)
+    assert int(se.K[0, 0]) == 1 and bool(se.conv[0, 0])
+    np.testing.assert_array_equal(se.llr[0, 0], [-1.0, -1.0, 3.0])
+    assert int(fl.K[0, 0]) == 2 and bool(fl.conv[0, 0])
+    np.testing.assert_array_equal(fl.llr[0, 0], [-1.0, -1.0, 1.0])
+
+
+@pytest.mark.parametrize("schedule", [oracle.FLOODING, oracle.LAYERED])
+def test_halting_iteration_one_and_never(schedule):
+    """One check {v0, v1}, s = 1, mu = (1, 3).  After one iteration r(->v0) = -3 alpha,
+    r(->v1) = -alpha, and every later iteration repeats it (each variable has one
+    check, so q = mu).  alpha = 1/2: P = (-0.5, 2.5), e = (1, 0) meets s at t = 1.
+    alpha = 1/4: P = (0.25, 2.75), e = 0 never meets s: not converged, K = T."""
+    h = np.array([[1, 1]], np.uint8)
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    syn = oracle.pack(np.array([[1]], np.uint8))
+    mu = np.array([1.0, 3.0])
+    a = oracle.decode(h, bp, rows, syn, mu, T=7, schedule=schedule, alpha=0.5, want_llr=True)
+    assert int(a.K[0, 0]) == 1 and bool(a.conv[0, 0])
+    np.testing.assert_array_equal(a.llr[0, 0], [-0.5, 2.5])
+    b = oracle.decode(h, bp, rows, syn, mu, T=7, schedule=schedule, alpha=0.25, want_llr=True)
+    assert int(b.K[0, 0]) == 7 and not bool(b.conv[0, 0]) and int(b.chosen[0]) == -1
+    np.testing.assert_array_equal(b.llr[0, 0], [0.25, 2.75])
+
+
+def test_halting_with_a_zero_posterior():
+    """A posterior of exactly 0 decides e = 0 (ties go to 0, Section II-B's hard
+    decision).  Chain, s = (0, 1), mu = (2, 1, 4), alpha = 1/2, flooding:
+      t=1: r(c0->v0) = 0.5, r(c0->v1) = 1, r(c1->v1) = -2, r(c1->v2) = -0.5,
+           P = (2.5, 0, 3.5), e = 0, c1 unmet;
+      t=2: q(v1->c0) = -1, q(v1->c1) = 2: r(c0->v0) = -0.5, r(c0->v1) = 1,
+           r(c1->v1) = -2, r(c1->v2) = -1, P = (1.5, 0, 3), e = 0;
+      later iterations repeat t=2: never converges, K = T."""
+    h = _chain()
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    syn = oracle.pack(np.array([[0, 1]], np.uint8))
+    mu = np.array([2.0, 1.0, 4.0])
+    r1 = oracle.decode(h, bp, rows, syn, mu, T=1, alpha=0.5, want_llr=True)
+    np.testing.assert_array_equal(r1.llr[0, 0], [2.5, 0.0, 3.5])
+    r = oracle.decode(h, bp, rows, syn, mu, T=9, alpha=0.5, want_llr=True)
+    assert int(r.K[0, 0]) == 9 and not bool(r.conv[0, 0])
+    np.testing.assert_array_equal(r.llr[0, 0], [1.5, 0.0, 3.0])
+    assert not oracle.unpack(r.cand[0, 0], 3).any()
+
+
+def test_fixed_T_reports_the_first_halting_iteration():
+    """Diagnostic fixed-T mode: K is the first iteration whose decision met the
+    syndrome, the posterior is the state after T.  Chain as above (K = 2, a fixed
+    point from t = 2 on), and the single check with alpha = 1/2 (K = 1)."""
+    h = _chain()
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    syn = oracle.pack(np.array([[0, 1]], np.uint8))
+    r = oracle.decode(h, bp, rows, syn, np.array([2.0, 1.0, 4.0]), T=6, alpha=1.0, fixed_T=True, want_llr=True)
+    assert int(r.K[0, 0]) == 2 and bool(r.conv[0, 0])
+    np.testing.assert_array_equal(r.llr[0, 0], [-1.0, -1.0, 1.0])
+
+
+# ------------------------------------------------------------------ representations: subtree order
+
+def _alg2_reference(h, perm):
+    """Algorithm 2 written again for this test from the paper's description
+    (Section III-A): roots in pi order; from a root, checks are examined first in,
+    first out; a check joins the growing subtree when at most one of its
+    variables is already covered (and it is still unassigned), then its
+    variables are covered and their untested unassigned checks queued in
+    ascending order.  Covered/tested marks start afresh for each root.  Returns
+    the subtrees as row lists in acceptance order."""
+    from collections import deque
+    m, n = h.shape
+    rows_of = [list(np.nonzero(h[j])[0]) for j in range(m)]
+    checks_of = [list(np.nonzero(h[:, v])[0]) for v in range(n)]
+    owner = [None] * m
+    out = []
+    for root in perm:
+        if owner[root] is not None:
+            continue
+        tree = []
+        covered, tested = set(), set()
+        q = deque([root])
+        while q:
+            u = q.popleft()
+            tested.add(u)
+            if owner[u] is not None or sum(v in covered for v in rows_of[u]) > 1:
+                continue
+            owner[u] = len(out)
+            tree.append(int(u))
+            for v in rows_of[u]:
+                covered.add(v)
+                q.extend(c for c in checks_of[v] if c not in tested and owner[c] is None)
+        out.append(tree)
+    return out
+
+
+def test_alg2_reference_reproduces_fig2():
+    h, perm, cs_expect, subs = _read_fig2()
+    got = _alg2_reference(h, perm)
+    assert got == [subs[s] for s in sorted(subs)]
+
+
+@pytest.mark.parametrize("factory,L", [(codes.bb72, 4), (codes.bb144, 16), (codes.bb288, 32)])
+def test_subtree_mode_selection_order(factory, L):
+    """Representations of the subtrees mode: the first L distinct subtrees (as row
+    sets) met while walking pi_0, pi_1, ... in discovery order, each with its rows
+    in acceptance order.  The expected list comes from the reference Algorithm 2
+    above, not from the oracle."""
+    c = factory()
+    for h in (c.hx, c.hz):
+        perms = check_permutations(h.shape[0], 8, seed=0)
+        expect, seen = [], set()
+        for perm in perms:
+            for t in _alg2_reference(h, perm):
+                key = frozenset(t)
+                if key not in seen and len(expect) < L:
+                    seen.add(key)
+                    expect.append(t)
+        bp, rows = oracle.build_bases(h, "subtrees", L, perms)
+        got = [rows[bp[l]:bp[l + 1]].tolist() for l in range(L)]
+        assert got == expect
+
+
+def test_ramp_mode_prefixes():
+    """Ramp mode: representation l appends the first round(l m / (L - 1)) rows (halves
+    up) of pi_l's acceptance order (the reference Algorithm 2's subtrees joined)."""
+    c = codes.bb288()
+    h = c.hz
+    L = 32
+    perms = check_permutations(h.shape[0], L, seed=0)
+    bp, rows = oracle.build_bases(h, "ramp", L, perms)
+    m = h.shape[0]
+    for l in range(L):
+        r = (2 * l * m + (L - 1)) // (2 * (L - 1))
+        joined = [x for t in _alg2_reference(h, perms[l]) for x in t]
+        assert rows[bp[l]:bp[l + 1]].tolist() == joined[:r]
+
+
 # ------------------------------------------------------------------ list decision
 
 def test_decision_rules_worked_example():
