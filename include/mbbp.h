@@ -185,7 +185,9 @@ enum {
     MBBP_CNT_SUM_K = 4,       /* sum over (shot, part, representation) of iterations */
     MBBP_CNT_EDGE_UPDATES = 5,/* sum of iterations x edges of that representation */
     MBBP_CNT_NOCONV = 6,      /* (shot, part) pairs where no representation converged */
-    MBBP_CNT_TIES = 7,        /* (shot, part) pairs whose least weight is shared by distinct candidates */
+    MBBP_CNT_TIES = 7,        /* (shot, part) pairs whose best value under the decision rule is shared
+                                 by distinct converged candidates (least weight: the same weight; FWS:
+                                 the same score); the smaller index decides those */
     MBBP_NUM_COUNTERS = 8
 };
 
@@ -223,11 +225,33 @@ mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, 
                           mbbp_launch_config *chosen);
 
 /* mbbp_run replays a HIP graph captured per `shots` (enable = 1, default) or
- * launches its kernels directly (enable = 0); results are identical. */
+ * launches its kernels directly (enable = 0); results are identical.  A graph
+ * captured before the batched launch configuration changed (mbbp_set_config,
+ * mbbp_autotune) is captured again. */
 mbbp_status mbbp_set_graph(mbbp_ctx *ctx, int32_t enable);
 
+/* The launch configuration held by the BP kernel node of the graph mbbp_run has
+ * captured for `shots` (waves_per_block and blocks read from the node itself).
+ * MBBP_EINVAL if no graph is captured for that size. */
+mbbp_status mbbp_run_graph_config(mbbp_ctx *ctx, int64_t shots, mbbp_launch_config *cfg);
+
+/* Uniform prior LLR of one part (the BP initialisation of Section II-B),
+ * log((1 - q) / q) rounded to float, with q the part's flip probability: 2p/3
+ * under depolarizing noise (X and Y, or Y and Z, flip it), p under X-only noise.
+ * This is the prior mbbp_run and mbbp_autotune use.  MBBP_EINVAL unless
+ * 0 < q < 1 or for an unknown model. */
+mbbp_status mbbp_prior_llr(int32_t noise, double p, float *mu);
+
+/* mbbp_decode as the naive per-basis form (enable = 1): one BP launch per (part,
+ * representation), each over all shots, instead of one launch over every
+ * representation of both parts.  Results are identical (for comparison with the
+ * batched form).  Default 0. */
+mbbp_status mbbp_set_per_basis(mbbp_ctx *ctx, int32_t enable);
+
 /* Event timing of the BP kernel.  While enabled, every BP kernel launch of this
- * context is bracketed by HIP events recorded on the launch's stream.
+ * context is bracketed by HIP events recorded on the launch's stream (under
+ * mbbp_run's graph replay by the graph's own event record nodes around its BP
+ * kernel node, given fresh events at every replay).
  * mbbp_bp_time waits for those events and returns the summed elapsed time (ms)
  * and the number of launches since the last reset (reset != 0 clears them). */
 mbbp_status mbbp_set_timing(mbbp_ctx *ctx, int32_t enable);

@@ -195,7 +195,9 @@ class Decoder:
         _need(syn_x, "syn_x", (shots, (self.mz + 63) // 64), torch.int64)
         _need(syn_z, "syn_z", (shots, (self.mx + 63) // 64), torch.int64)
         _need(prior_x, "prior_x", _prior_shape(prior_x, shots, self.n), torch.float32)
-        _need(prior_z, "prior_z", _prior_shape(prior_x, shots, self.n), torch.float32)
+        _need(prior_z, "prior_z", _prior_shape(prior_z, shots, self.n), torch.float32)
+        if prior_x.dim() != prior_z.dim():
+            raise ValueError("prior_x and prior_z: both per shot or both one vector")
         if out is None:
             out = dict(corr_x=self._dev((shots, self.W), torch.int64),
                        corr_z=self._dev((shots, self.W), torch.int64),
@@ -265,6 +267,18 @@ class Decoder:
     def set_noise(self, model: int) -> None:
         """Noise model of sample(), run() and autotune(): DEPOLARIZING or X_ONLY."""
         _lib.check(_lib.lib().mbbp_set_noise(self._ctx, int(model)), "mbbp_set_noise")
+
+    def set_per_basis(self, enable: bool) -> None:
+        """decode() as one BP launch per (part, representation): the naive form."""
+        _lib.check(_lib.lib().mbbp_set_per_basis(self._ctx, 1 if enable else 0), "mbbp_set_per_basis")
+
+    def run_graph_config(self, shots: int) -> dict:
+        """Launch shape held by the BP kernel node of run()'s graph for `shots`."""
+        cfg = _lib.LaunchConfig()
+        _lib.check(_lib.lib().mbbp_run_graph_config(self._ctx, int(shots), ctypes.byref(cfg)),
+                   "mbbp_run_graph_config")
+        return dict(lanes_per_instance=cfg.lanes_per_instance, waves_per_block=cfg.waves_per_block,
+                    chunk=cfg.chunk, blocks=cfg.blocks)
 
     def set_graph(self, enable: bool) -> None:
         _lib.check(_lib.lib().mbbp_set_graph(self._ctx, 1 if enable else 0), "mbbp_set_graph")
@@ -352,10 +366,12 @@ class Decoder:
         return counters
 
 
-def prior_llr(p: float) -> float:
-    """Depolarizing prior: each error type flips with probability 2p/3 (Section II-B)."""
-    q = 2.0 * p / 3.0
-    return float(np.log((1.0 - q) / q))
+def prior_llr(p: float, noise: int = DEPOLARIZING) -> float:
+    """The library's uniform prior LLR of one part (Section II-B initialisation) at
+    error rate p under `noise`, as a float32 value (mbbp_prior_llr)."""
+    mu = ctypes.c_float()
+    _lib.check(_lib.lib().mbbp_prior_llr(int(noise), float(p), ctypes.byref(mu)), "mbbp_prior_llr")
+    return float(mu.value)
 
 
 def words_to_numpy(t) -> np.ndarray:

@@ -465,6 +465,12 @@ void bp_wave_kernel(BPArgs a) {
 
 size_t bp_lds_limit() { return 64 * 1024; }  // per workgroup
 
+// The BP kernel function most recently launched by this host thread (graph capture
+// records which node is the BP kernel).
+static thread_local const void *t_last_bp_kernel = nullptr;
+const void *last_bp_kernel() { return t_last_bp_kernel; }
+void set_last_bp_kernel(const void *f) { t_last_bp_kernel = f; }
+
 // Instantiated (PV, PC): variable and check passes of 64 lanes.
 struct PassPair {
     int pv, pc;
@@ -521,6 +527,7 @@ static hipError_t launch_wave_t(const BPArgs &a, const BPConfig &cfg, hipStream_
     const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
     hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE, SCHED>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
                        a);
+    set_last_bp_kernel(reinterpret_cast<const void *>(&bp_wave_kernel<PV, PC, DC, RULE, SCHED>));
     return hipGetLastError();
 }
 
@@ -542,7 +549,6 @@ static hipError_t launch_pair(const BPArgs &a, const BPConfig &cfg, int rule, hi
 
 template <int SCHED>
 static hipError_t launch_sched(const BPArgs &a, const BPConfig &cfg, int rule, const PassPair &pp, hipStream_t s) {
-#ifndef MBBP_KERNEL_PROBE
     switch (pp.pv * 100 + pp.pc) {
     case 101: return launch_pair<1, 1, SCHED>(a, cfg, rule, s);
     case 201: return launch_pair<2, 1, SCHED>(a, cfg, rule, s);
@@ -554,9 +560,6 @@ static hipError_t launch_sched(const BPArgs &a, const BPConfig &cfg, int rule, c
     case 1414: return launch_pair<14, 14, SCHED>(a, cfg, rule, s);
     case 1616: return launch_pair<16, 16, SCHED>(a, cfg, rule, s);
     }
-#else
-    (void)a; (void)cfg; (void)rule; (void)pp; (void)s;
-#endif
     return hipErrorInvalidValue;
 }
 

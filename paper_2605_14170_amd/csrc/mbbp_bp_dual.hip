@@ -377,6 +377,7 @@ hipError_t launch_dual_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
     const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
     hipLaunchKernelGGL((bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
                        a);
+    set_last_bp_kernel(reinterpret_cast<const void *>(&bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>));
     return hipGetLastError();
 }
 

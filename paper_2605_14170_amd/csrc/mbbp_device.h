@@ -209,5 +209,8 @@ bool bp_dual_fits(int n, int mmax);  // a part of n variables and mmax + 1 posit
 hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s);
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();
+// BP kernel function most recently launched by the calling host thread.
+const void *last_bp_kernel();
+void set_last_bp_kernel(const void *f);
 
 }  // namespace mbbp

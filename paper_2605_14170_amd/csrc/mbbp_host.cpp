@@ -415,11 +415,16 @@ mbbp_status upload(DevBuf &b, const std::vector<T> &v) {
 
 // ----------------------------------------------------------------------------- context
 
+// A captured mbbp_run: its BP kernel node was launched with `cfg`; the two event
+// record nodes around it take fresh events at every timed replay.
 struct RunGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t prep = nullptr;
     hipKernelNodeParams prep_params{};
+    hipGraphNode_t ev_node[2] = {nullptr, nullptr};
+    const void *bp_func = nullptr;
+    mbbp::BPConfig cfg{};
 };
 
 struct mbbp_ctx {
@@ -455,6 +460,9 @@ struct mbbp_ctx {
     hipStream_t capture_stream = nullptr;
     std::map<int64_t, RunGraph> graphs;
     bool use_graph = true;  // mbbp_run replays a captured graph
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};  // events of the captured record nodes (untimed replays)
+    bool per_basis = false;  // mbbp_decode: one BP launch per (part, representation)
+    const int32_t *rep_ids = nullptr;  // device [2L]: p * L + l in order (single-pair launches)
     // BP kernel event timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -607,7 +615,7 @@ struct WeightedCall {
 mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint64_t *const syn[2],
                    const float *const prior[2], int pps, uint64_t *const cand[2], uint16_t *const kstat[2],
                    float *const llr[2], bool persistent, hipStream_t s, const WeightedCall *wc = nullptr,
-                   bool rep_major = true) {
+                   bool rep_major = true, hipEvent_t *capture_ev = nullptr) {
     const int rule = wc ? (int)MBBP_WEIGHTED : c->params.rule;
     if (rule == MBBP_WEIGHTED && !wc && (!c->walpha || !c->wbeta))
         return fail(MBBP_EINVAL, "weighted rule: no weights set (mbbp_set_weights)");
@@ -669,15 +677,33 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         run.waves_per_block /= 2;
     if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
         return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
+    // timing: events around the launch(es); under capture (mbbp_run) the graph's own
+    // event record nodes are recorded instead and given fresh events per replay
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (c->timing) {
+    if (capture_ev) {
+        MBBP_HIP(hipEventRecord(capture_ev[0], s));
+    } else if (c->timing) {
         MBBP_HIP(hipEventCreate(&ev0));
         MBBP_HIP(hipEventCreate(&ev1));
         MBBP_HIP(hipEventRecord(ev0, s));
     }
-    hipError_t e = mbbp::launch_bp(a, run, c->schedule, rule, s);
+    hipError_t e = hipSuccess;
+    if (!persistent && c->per_basis && !wc && nparts == 2) {
+        // the naive form: one launch per (part, representation) over all shots
+        for (int k = 0; k < a.n_pl && e == hipSuccess; ++k) {
+            mbbp::BPArgs one = a;
+            one.item_order = c->rep_ids + k;
+            one.n_pl = 1;
+            one.n_items = a.n_chunks;
+            e = mbbp::launch_bp(one, run, c->schedule, rule, s);
+        }
+    } else {
+        e = mbbp::launch_bp(a, run, c->schedule, rule, s);
+    }
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("bp launch: ") + hipGetErrorString(e));
-    if (c->timing) {
+    if (capture_ev) {
+        MBBP_HIP(hipEventRecord(capture_ev[1], s));
+    } else if (c->timing) {
         MBBP_HIP(hipEventRecord(ev1, s));
         c->events.push_back({ev0, ev1});
     }
@@ -892,6 +918,11 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
             (void)Ws;
         }
         if ((st = c->alloc(c->w_queue, 1)) != MBBP_OK) return st;
+        {
+            std::vector<int32_t> ids(2 * c->dp[0].L);
+            for (size_t i = 0; i < ids.size(); ++i) ids[i] = (int32_t)i;
+            if ((st = c->put(c->rep_ids, ids)) != MBBP_OK) return st;
+        }
         // heavy-first order of (part, representation) work for the persistent form
         {
             std::vector<std::pair<int64_t, int32_t>> w;
@@ -924,6 +955,8 @@ void mbbp_destroy(mbbp_ctx *ctx) {
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    for (hipEvent_t ev : ctx->graph_ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -995,12 +1028,6 @@ static void thresholds(double p, int noise, uint64_t t[3]) {
     for (int k = 1; k <= 3; ++k) t[k - 1] = (uint64_t)std::floor((double)k * (p / 3.0) * 4294967296.0);
 }
 
-// Flip probability of each part under the context's noise model (the uniform
-// prior log((1 - q) / q) of mbbp_run): 2p/3 depolarizing, p for X errors only.
-static double part_flip_prob(const mbbp_ctx *ctx, double p) {
-    return ctx->noise == MBBP_NOISE_X_ONLY ? p : 2.0 * p / 3.0;
-}
-
 mbbp_status mbbp_set_noise(mbbp_ctx *ctx, int32_t model) {
     if (!ctx) return fail(MBBP_EINVAL, "null ctx");
     if (model != MBBP_NOISE_DEPOLARIZING && model != MBBP_NOISE_X_ONLY) return fail(MBBP_EINVAL, "unknown noise model");
@@ -1053,7 +1080,8 @@ mbbp_status mbbp_failures(mbbp_ctx *ctx, int64_t shots, const uint64_t *err_x, c
 // and syndromes, persistent BP, decision with counters, failure test, counters
 // added into the caller's.  Every node reads its per-call values from the device
 // descriptor, so a captured copy is replayed by changing only the prep node.
-static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int64_t shots, hipStream_t s) {
+static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int64_t shots, hipStream_t s,
+                               hipEvent_t *capture_ev = nullptr) {
     hipError_t e = mbbp::launch_run_prep(prep, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("prep launch: ") + hipGetErrorString(e));
     mbbp::SampleArgs sa{};
@@ -1070,7 +1098,9 @@ static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int
     const float *pr[2] = {ctx->w_prior[0], ctx->w_prior[1]};
     float *ll[2] = {nullptr, nullptr};
     mbbp_status st;
-    if ((st = run_bp(ctx, 0, 2, shots, sy, pr, 0, ctx->cand, ctx->kstat, ll, true, s)) != MBBP_OK) return st;
+    if ((st = run_bp(ctx, 0, 2, shots, sy, pr, 0, ctx->cand, ctx->kstat, ll, true, s, nullptr, true, capture_ev)) !=
+        MBBP_OK)
+        return st;
     if ((st = run_select(ctx, 0, 2, shots, ctx->w_corr, ctx->w_conv, ctx->w_basis, ctx->w_counters, ctx->w_kmax,
                          s)) != MBBP_OK)
         return st;
@@ -1090,10 +1120,28 @@ static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int
     return MBBP_OK;
 }
 
+static bool same_config(const mbbp::BPConfig &a, const mbbp::BPConfig &b) {
+    return a.lpi == b.lpi && a.waves_per_block == b.waves_per_block && a.chunk == b.chunk && a.blocks == b.blocks;
+}
+
+static void drop_graphs(mbbp_ctx *ctx) {
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    ctx->graphs.clear();
+}
+
 static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int64_t shots, RunGraph &g) {
     if (!ctx->capture_stream) MBBP_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    for (hipEvent_t &ev : ctx->graph_ev)
+        if (!ev) MBBP_HIP(hipEventCreate(&ev));
     MBBP_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
-    mbbp_status st = run_enqueue(ctx, prep, shots, ctx->capture_stream);
+    mbbp::set_last_bp_kernel(nullptr);
+    mbbp_status st = run_enqueue(ctx, prep, shots, ctx->capture_stream, ctx->graph_ev);
+    g.bp_func = mbbp::last_bp_kernel();
+    g.cfg = ctx->batched_cfg;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
     if (st != MBBP_OK) {
@@ -1106,9 +1154,17 @@ static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &pre
     MBBP_HIP(hipGraphGetNodes(graph, nullptr, &count));
     std::vector<hipGraphNode_t> nodes(count);
     MBBP_HIP(hipGraphGetNodes(graph, nodes.data(), &count));
+    int n_ev = 0;
     for (hipGraphNode_t nd : nodes) {
         hipGraphNodeType ty;
         MBBP_HIP(hipGraphNodeGetType(nd, &ty));
+        if (ty == hipGraphNodeTypeEventRecord) {
+            hipEvent_t ev = nullptr;
+            MBBP_HIP(hipGraphEventRecordNodeGetEvent(nd, &ev));
+            for (int k = 0; k < 2; ++k)
+                if (ev == ctx->graph_ev[k]) g.ev_node[k] = nd;
+            ++n_ev;
+        }
         if (ty != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams kp;
         MBBP_HIP(hipGraphKernelNodeGetParams(nd, &kp));
@@ -1118,6 +1174,8 @@ static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &pre
         }
     }
     if (!g.prep) return fail(MBBP_EDEVICE, "captured graph has no preparation node");
+    if (n_ev != 2 || !g.ev_node[0] || !g.ev_node[1])
+        return fail(MBBP_EDEVICE, "captured graph lacks the BP timing event nodes");
     MBBP_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
     return MBBP_OK;
 }
@@ -1131,7 +1189,6 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     mbbp_status st = ensure_run_workspace(ctx);
     if (st != MBBP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const double q = part_flip_prob(ctx, p);
     mbbp::RunPrepArgs prep{};
     prep.d.seed = seed;
     prep.d.shot0 = shot0;
@@ -1143,13 +1200,21 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     prep.prior0 = ctx->w_prior[0];
     prep.prior1 = ctx->w_prior[1];
     prep.n = ctx->n;
-    prep.mu = (float)std::log((1.0 - q) / q);
+    if ((st = mbbp_prior_llr(ctx->noise, p, &prep.mu)) != MBBP_OK) return st;
     prep.kmax = ctx->w_kmax;
     prep.shots = shots;
     prep.queue = ctx->w_queue;
     prep.counters = ctx->w_counters;
-    if (ctx->timing || !ctx->use_graph) return run_enqueue(ctx, prep, shots, s);  // events need direct launches
+    if (!ctx->use_graph) return run_enqueue(ctx, prep, shots, s);
     auto it = ctx->graphs.find(shots);
+    if (it != ctx->graphs.end() && !same_config(it->second.cfg, ctx->batched_cfg)) {
+        // captured with another launch shape: capture again
+        (void)hipStreamSynchronize(s);
+        if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+        if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+        ctx->graphs.erase(it);
+        it = ctx->graphs.end();
+    }
     if (it == ctx->graphs.end()) {
         RunGraph g;
         st = capture_run_graph(ctx, prep, shots, g);
@@ -1166,8 +1231,40 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     kp.kernelParams = args;
     kp.extra = nullptr;
     MBBP_HIP(hipGraphExecKernelNodeSetParams(g.exec, g.prep, &kp));
+    hipEvent_t ev[2] = {ctx->graph_ev[0], ctx->graph_ev[1]};
+    if (ctx->timing) {
+        MBBP_HIP(hipEventCreate(&ev[0]));
+        MBBP_HIP(hipEventCreate(&ev[1]));
+    }
+    for (int k = 0; k < 2; ++k) MBBP_HIP(hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_node[k], ev[k]));
     MBBP_HIP(hipGraphLaunch(g.exec, s));
+    if (ctx->timing) ctx->events.push_back({ev[0], ev[1]});
     return MBBP_OK;
+}
+
+mbbp_status mbbp_run_graph_config(mbbp_ctx *ctx, int64_t shots, mbbp_launch_config *cfg) {
+    if (!ctx || !cfg) return fail(MBBP_EINVAL, "null argument");
+    auto it = ctx->graphs.find(shots);
+    if (it == ctx->graphs.end()) return fail(MBBP_EINVAL, "no graph captured for this number of shots");
+    const RunGraph &g = it->second;
+    size_t count = 0;
+    MBBP_HIP(hipGraphGetNodes(g.graph, nullptr, &count));
+    std::vector<hipGraphNode_t> nodes(count);
+    MBBP_HIP(hipGraphGetNodes(g.graph, nodes.data(), &count));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        MBBP_HIP(hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        MBBP_HIP(hipGraphKernelNodeGetParams(nd, &kp));
+        if (kp.func != g.bp_func) continue;
+        cfg->lanes_per_instance = 64;
+        cfg->waves_per_block = (int32_t)(kp.blockDim.x / 64);
+        cfg->chunk = g.cfg.chunk;
+        cfg->blocks = (int32_t)kp.gridDim.x;
+        return MBBP_OK;
+    }
+    return fail(MBBP_EDEVICE, "captured graph has no BP kernel node");
 }
 
 static bool config_fits(const mbbp_ctx *c, int lpi) {
@@ -1188,8 +1285,12 @@ mbbp_status mbbp_set_config(mbbp_ctx *ctx, int32_t form, const mbbp_launch_confi
     if (cfg->blocks < 0) return fail(MBBP_EINVAL, "blocks < 0");
     if (!config_fits(ctx, lpi)) return fail(MBBP_EUNSUPPORTED, "code too large for this lane count");
     mbbp::BPConfig b{lpi, cfg->waves_per_block, cfg->chunk, cfg->blocks > 0 ? cfg->blocks : ctx->cu_count * 4};
-    if (form == 0) ctx->plain_cfg = b;
-    else ctx->batched_cfg = b;
+    if (form == 0) {
+        ctx->plain_cfg = b;
+    } else {
+        if (!same_config(ctx->batched_cfg, b)) drop_graphs(ctx);  // captured launches hold the old shape
+        ctx->batched_cfg = b;
+    }
     return MBBP_OK;
 }
 
@@ -1201,6 +1302,21 @@ mbbp_status mbbp_get_config(mbbp_ctx *ctx, int32_t form, mbbp_launch_config *cfg
     cfg->waves_per_block = b.waves_per_block;
     cfg->chunk = b.chunk;
     cfg->blocks = b.blocks;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_prior_llr(int32_t noise, double p, float *mu) {
+    if (!mu) return fail(MBBP_EINVAL, "null mu");
+    if (noise != MBBP_NOISE_DEPOLARIZING && noise != MBBP_NOISE_X_ONLY) return fail(MBBP_EINVAL, "unknown noise model");
+    const double q = noise == MBBP_NOISE_X_ONLY ? p : 2.0 * p / 3.0;
+    if (!(q > 0.0 && q < 1.0)) return fail(MBBP_EINVAL, "flip probability outside (0, 1)");
+    *mu = (float)std::log((1.0 - q) / q);
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_set_per_basis(mbbp_ctx *ctx, int32_t enable) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    ctx->per_basis = enable != 0;
     return MBBP_OK;
 }
 
@@ -1223,8 +1339,9 @@ mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, 
     if ((st = mbbp_sample(ctx, seed, p, 0, shots, ctx->w_err[0], ctx->w_err[1], ctx->w_syn[0], ctx->w_syn[1], s)) !=
         MBBP_OK)
         return st;
-    const double q = part_flip_prob(ctx, p);
-    std::vector<float> mu(ctx->n, (float)std::log((1.0 - q) / q));
+    float mu0 = 0.0f;
+    if ((st = mbbp_prior_llr(ctx->noise, p, &mu0)) != MBBP_OK) return st;
+    std::vector<float> mu(ctx->n, mu0);
     for (int pt = 0; pt < 2; ++pt)
         MBBP_HIP(hipMemcpyAsync(ctx->w_prior[pt], mu.data(), mu.size() * 4, hipMemcpyHostToDevice, s));
     std::vector<mbbp::BPConfig> cands;
@@ -1270,6 +1387,7 @@ mbbp_status mbbp_autotune(mbbp_ctx *ctx, int32_t form, uint64_t seed, double p, 
     (void)hipEventDestroy(e1);
     ctx->timing = timing;
     slot = st == MBBP_OK ? best : keep;
+    if (form == 1 && !same_config(slot, keep)) drop_graphs(ctx);  // captured launches hold the old shape
     if (st != MBBP_OK) return st;
     if (chosen) {
         chosen->lanes_per_instance = best.lpi;
@@ -1323,15 +1441,6 @@ mbbp_status mbbp_edge_counts(mbbp_ctx *ctx, int32_t part, int64_t *edges) {
     if (part != 0 && part != 1) return fail(MBBP_EINVAL, "part must be 0 or 1");
     for (int l = 0; l < ctx->hp[part].L; ++l) edges[l] = ctx->hp[part].E[l];
     return MBBP_OK;
-}
-
-static void drop_graphs(mbbp_ctx *ctx) {
-    (void)hipDeviceSynchronize();
-    for (auto &kv : ctx->graphs) {
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-    }
-    ctx->graphs.clear();
 }
 
 mbbp_status mbbp_set_weights(mbbp_ctx *ctx, const float *alpha, const float *beta) {

@@ -186,7 +186,8 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
                 if (eq && k < lg) first = false;
                 if (eq && k >= lg) ++cnt;
             }
-            long long bc = first ? cnt : -1, bw1 = w + 1;
+            const long long my_c = first ? cnt : -1, my_w1 = w + 1;
+            long long bc = my_c, bw1 = my_w1;
             int bl = first ? lg : 0x7fff;
             for (int o = 1; o < G; o <<= 1) {
                 const long long oc = __shfl_xor(bc, o, 64), ow1 = __shfl_xor(bw1, o, 64);
@@ -200,6 +201,10 @@ __global__ __launch_bounds__(256) void select_kernel(SelectArgs a) {
                 if (take) { bc = oc; bw1 = ow1; bl = ol; }
             }
             best = bc < 0 ? -1 : bl;
+            // a tie: another distinct candidate (first occurrence) with the same score
+            const bool tie = best >= 0 && my_c >= 0 && lg != best && my_c * bw1 == bc * my_w1;
+            const uint64_t tb = __ballot(tie);
+            if (lg == 0 && ((G == 64 ? tb : (tb >> gbase) & ((1ull << G) - 1ull)) != 0)) ++c_ties;
         }
         if (live) {
             if (lg == 0) {

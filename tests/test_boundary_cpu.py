@@ -138,3 +138,30 @@ def test_set_noise_validates_arguments():
     assert lib.mbbp_set_noise(None, 0) == -1
     assert b"null ctx" in lib.mbbp_last_error()
     assert pk.DEPOLARIZING == 0 and pk.X_ONLY == 1 and oracle.BSC_X == pk.X_ONLY
+
+
+def test_partition_bases():
+    """Table II inputs: tree bases are the partition's subtrees in acceptance order;
+    matched random bases have the same sizes, distinct in-range rows, are seeded
+    and differ between partitions."""
+    import oracle
+    from workloads import codes
+    from workloads.partitions import matched_random_bases, tree_bases
+    from workloads.perms import check_permutations
+    h = codes.bb288().hz
+    m = h.shape[0]
+    perms = check_permutations(m, 3, seed=0)
+    subs = oracle.subtree_lists(h, perms[1])
+    bp, rows = tree_bases(subs)
+    assert [rows[bp[i]:bp[i + 1]].tolist() for i in range(len(subs))] == subs
+    bp2, rows2 = tree_bases(subs, count=len(subs) + 3)
+    assert rows2[bp2[len(subs)]:].tolist() == [x for s in subs[:3] for x in s]
+    rb, rr = matched_random_bases(subs, m, seed=5, k=1)
+    np.testing.assert_array_equal(np.diff(rb), [len(s) for s in subs])
+    for i in range(len(subs)):
+        r = rr[rb[i]:rb[i + 1]]
+        assert len(set(r.tolist())) == len(r) and (r >= 0).all() and (r < m).all()
+    rb_again, rr_again = matched_random_bases(subs, m, seed=5, k=1)
+    np.testing.assert_array_equal(rr, rr_again)
+    _, rr_other = matched_random_bases(subs, m, seed=5, k=2)
+    assert rr_other.tolist() != rr.tolist()
