@@ -509,28 +509,72 @@ static real wnms_msg(const real *qin, int d, int skip, int sbit, real alpha, rea
     return clampr(wsum, rmax, hit);
 }
 
-/* phi(x) = ln((e^x + 1) / (e^x - 1)), its own inverse; phi(0) = inf, phi(inf) = 0 */
-static real phi(real x) {
-    if (x <= 0) return (real)INFINITY;
+/* Sum-product (tanh rule, Section II-B): the magnitude of the message to slot
+ * `skip` is phi(S) with S = sum over the other slots of phi(|q|), where
+ * phi(x) = ln((e^x + 1) / (e^x - 1)) = ln coth(x / 2), its own inverse, phi(0) = inf,
+ * phi(inf) = 0; equivalently 2 atanh(prod tanh(|q| / 2)).
+ *
+ * The magnitudes reach r_max (2^16), far beyond where e^-x is representable, and
+ * the message there is about the smallest |q| (exactly min |q| - ln(1 + ...)), not
+ * r_max.  So the sum is taken in the log domain: ln phi(x) per slot, S through a
+ * log-sum-exp, and phi(S) from ln S.  Every branch below is the same function;
+ * the cut-offs only choose the form whose terms stay representable, and the
+ * neglected terms are below 1e-26 relative.                                      */
 #if defined(ORACLE_SINGLE) /* set together with -DREAL=float */
-    return log1pf(2.0f / expm1f(x));
+#define RLOG logf
+#define REXP expf
+#define RLOG1P log1pf
+#define REXPM1 expm1f
+#define RLN2 0.69314718f
 #else
-    return log1p(2.0 / expm1(x));
+#define RLOG log
+#define REXP exp
+#define RLOG1P log1p
+#define REXPM1 expm1
+#define RLN2 0.69314718055994531
 #endif
+
+/* ln phi(x), x > 0: phi(x) = log1p(v) with v = 2 / expm1(x), and
+ * ln v = ln 2 - x - log1p(-e^-x); for v < e^-30, ln log1p(v) = ln v - v/2 + O(v^2). */
+static real ln_phi(real x) {
+    if (x <= 0) return (real)INFINITY;
+    real lnv = RLN2 - x - RLOG1P(-REXP(-x));
+    if (lnv > (real)-30) return RLOG(RLOG1P(REXP(lnv)));
+    return lnv - (real)0.5 * REXP(lnv);
+}
+
+/* phi(S) given ln S: direct for moderate S (underflowing to 0 once phi(S) < 1e-300
+ * is below every representable magnitude of interest); for S < e^-30,
+ * phi(S) = ln(2 / S) + S^2 / 12 + O(S^4).                                        */
+static real phi_from_ln(real lnS) {
+    if (lnS == (real)INFINITY) return 0;
+    if (lnS > (real)-30) return RLOG1P((real)2 / REXPM1(REXP(lnS)));
+    return RLN2 - lnS + REXP((real)2 * lnS) / (real)12;
 }
 
 /* sum-product (tanh rule): sign product times phi(sum phi(|q|)), with syndrome sign */
 static real spa_msg(const real *qin, int d, int skip, int sbit, real rmax, int *hit, double *msign) {
-    real acc = 0;
-    int neg = sbit;
+    real lp[64];
+    real lmax = -(real)INFINITY;
+    int neg = sbit, cnt = 0;
     for (int k = 0; k < d; ++k) {
         if (k == skip) continue;
         real a = qin[k] < 0 ? -qin[k] : qin[k];
         if ((double)a < *msign) *msign = (double)a;
-        acc += phi(a);
+        lp[cnt] = ln_phi(a);
+        if (lp[cnt] > lmax) lmax = lp[cnt];
+        ++cnt;
         if (qin[k] < 0) neg ^= 1;
     }
-    real mag = phi(acc);
+    real lnS;
+    if (cnt == 0 || lmax == (real)INFINITY) {
+        lnS = lmax;  /* no other slot: phi(-inf) handled below; a zero |q|: S = inf */
+    } else {
+        real acc = 0;
+        for (int k = 0; k < cnt; ++k) acc += REXP(lp[k] - lmax);
+        lnS = lmax + RLOG(acc);
+    }
+    real mag = cnt == 0 ? (real)INFINITY : phi_from_ln(lnS);
     real r = neg ? -mag : mag;
     return clampr(r, rmax, hit);
 }
@@ -731,6 +775,7 @@ int orc_decode(int m, int n, const int *row_ptr, const int *col_idx,
             }
         }
     }
+    if (status == ORC_OK && maxd > 64) status = ORC_EINVAL; /* spa_msg keeps one slot buffer of 64 */
     int wn = words64(n), ws = words64(m);
     bp_work w;
     w.q = (real *)malloc(sizeof(real) * (size_t)(maxE + 1));

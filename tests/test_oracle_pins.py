@@ -389,6 +389,33 @@ def test_min_sum_is_min_cost_on_trees(schedule):
                                    rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("precision,rtol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_sum_product_large_magnitudes(precision, rtol):
+    """The tanh rule at magnitudes up to the clamp (the messages of the serial schedule
+    on codes with cycles get there).  One check, T = 1, so P_0 = mu_0 + r(c -> v0).
+    Weight 2: r = +-phi(phi(|mu_1|)) = +-|mu_1| (phi is its own inverse).  Weight 3:
+    2 atanh(tanh(a/2) tanh(b/2)) has the closed form
+    min(a, b) - ln(1 + e^-|a-b|) + ln(1 + e^-(a+b)).  Beyond r_max the message is
+    clamped."""
+    bp, rows = np.array([0, 0], np.int32), np.array([], np.int32)
+    for a in (0.3, 5.0, 50.0, 500.0, 5000.0, 60000.0):
+        for s in (0, 1):
+            res = oracle.decode(np.array([[1, 1]], np.uint8), bp, rows, oracle.pack(np.array([[s]], np.uint8)),
+                                np.array([1.0, a]), T=1, rule=oracle.SPA, fixed_T=True, want_llr=True,
+                                precision=precision)
+            assert res.llr[0, 0, 0] == pytest.approx(1.0 + (-a if s else a), rel=rtol)
+    for a, b in ((3.0, 4.0), (40.0, 41.5), (800.0, 800.25), (2000.0, 1999.0), (7000.0, 9000.0)):
+        res = oracle.decode(np.array([[1, 1, 1]], np.uint8), bp, rows, oracle.pack(np.array([[0]], np.uint8)),
+                            np.array([1.0, a, b]), T=1, rule=oracle.SPA, fixed_T=True, want_llr=True,
+                            precision=precision)
+        expect = min(a, b) - np.log1p(np.exp(-abs(a - b))) + np.log1p(np.exp(-(a + b)))
+        assert res.llr[0, 0, 0] == pytest.approx(1.0 + expect, rel=rtol)
+    res = oracle.decode(np.array([[1, 1]], np.uint8), bp, rows, oracle.pack(np.array([[0]], np.uint8)),
+                        np.array([1.0, 1e6]), T=1, rule=oracle.SPA, fixed_T=True, want_llr=True,
+                        precision=precision)
+    assert res.llr[0, 0, 0] == 1.0 + 65536.0 and bool(res.clamp[0, 0])
+
+
 def test_tree_from_a_code_subtree():
     """H_t of a maximal subtree, restricted to its variables, is a tree: sum-product on
     it is exact (the structure Section III-A builds on)."""
