@@ -415,6 +415,20 @@ mbbp_status upload(DevBuf &b, const std::vector<T> &v) {
 
 // ----------------------------------------------------------------------------- context
 
+// Buffers of the whole path of mbbp_run: allocated per context on first use, or
+// carved from the static scratch array by mbbp_run_static.
+struct RunWs {
+    uint64_t *err[2], *syn[2], *corr[2], *conv[2];
+    int16_t *basis[2];
+    float *prior[2];
+    int *kmax;
+    int64_t *counters;
+    mbbp::RunDesc *desc;
+    unsigned long long *queue;
+    uint64_t *cand[2];
+    uint16_t *kstat[2];
+};
+
 // A captured mbbp_run: its BP kernel node was launched with `cfg`; the two event
 // record nodes around it take fresh events at every timed replay.
 struct RunGraph {
@@ -615,7 +629,8 @@ struct WeightedCall {
 mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint64_t *const syn[2],
                    const float *const prior[2], int pps, uint64_t *const cand[2], uint16_t *const kstat[2],
                    float *const llr[2], bool persistent, hipStream_t s, const WeightedCall *wc = nullptr,
-                   bool rep_major = true, hipEvent_t *capture_ev = nullptr) {
+                   bool rep_major = true, bool capturing = false, unsigned long long *queue = nullptr) {
+    if (!queue) queue = c->w_queue;
     const int rule = wc ? (int)MBBP_WEIGHTED : c->params.rule;
     if (rule == MBBP_WEIGHTED && !wc && (!c->walpha || !c->wbeta))
         return fail(MBBP_EINVAL, "weighted rule: no weights set (mbbp_set_weights)");
@@ -656,7 +671,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     a.n_items = a.n_chunks * a.n_pl;
     a.item_order = persistent ? c->item_order + (part0 == 1 ? 0 : 0) : nullptr;
     if (persistent && nparts != 2) a.item_order = nullptr;
-    a.queue = c->w_queue;
+    a.queue = queue;
     if (!inst_layout(c, part0, nparts, pps != 0, c->schedule, rule, a))
         return fail(MBBP_EUNSUPPORTED, "code too large for the BP kernel's register tables");
     // two instances per wavefront where the paired kernel serves the launch
@@ -670,19 +685,17 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     mbbp::BPConfig run = cfg;
     if (persistent) {
         run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
-        hipError_t e = mbbp::launch_reset(c->w_queue, nullptr, 0, s);
+        hipError_t e = mbbp::launch_reset(queue, nullptr, 0, s);
         if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("reset launch: ") + hipGetErrorString(e));
     }
     while (run.waves_per_block > 1 && (size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
         run.waves_per_block /= 2;
     if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
         return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
-    // timing: events around the launch(es); under capture (mbbp_run) the graph's own
-    // event record nodes are recorded instead and given fresh events per replay
+    // timing: events around the launch(es); a captured launch (mbbp_run's graph) gets
+    // event record nodes of its own after capture, given fresh events per replay
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (capture_ev) {
-        MBBP_HIP(hipEventRecord(capture_ev[0], s));
-    } else if (c->timing) {
+    if (c->timing && !capturing) {
         MBBP_HIP(hipEventCreate(&ev0));
         MBBP_HIP(hipEventCreate(&ev1));
         MBBP_HIP(hipEventRecord(ev0, s));
@@ -701,9 +714,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         e = mbbp::launch_bp(a, run, c->schedule, rule, s);
     }
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("bp launch: ") + hipGetErrorString(e));
-    if (capture_ev) {
-        MBBP_HIP(hipEventRecord(capture_ev[1], s));
-    } else if (c->timing) {
+    if (c->timing && !capturing) {
         MBBP_HIP(hipEventRecord(ev1, s));
         c->events.push_back({ev0, ev1});
     }
@@ -712,7 +723,9 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
 
 mbbp_status run_select(mbbp_ctx *c, int part0, int nparts, int64_t shots, uint64_t *const corr[2],
                        uint64_t *const conv[2], int16_t *const basis[2], int64_t *counters, int *kmax,
-                       hipStream_t s) {
+                       hipStream_t s, uint64_t *const *cand = nullptr, uint16_t *const *kstat = nullptr) {
+    if (!cand) cand = c->cand;
+    if (!kstat) kstat = c->kstat;
     mbbp::SelectArgs a{};
     a.part[0] = c->dp[0];
     a.part[1] = c->dp[1];
@@ -721,8 +734,8 @@ mbbp_status run_select(mbbp_ctx *c, int part0, int nparts, int64_t shots, uint64
     a.rule = c->params.select;
     a.shots = shots;
     for (int p = 0; p < 2; ++p) {
-        a.cand[p] = c->cand[p];
-        a.kstat[p] = c->kstat[p];
+        a.cand[p] = cand[p];
+        a.kstat[p] = kstat[p];
         a.corr[p] = corr[p];
         a.conv[p] = conv[p];
         a.basis[p] = basis[p];
@@ -1081,7 +1094,7 @@ mbbp_status mbbp_failures(mbbp_ctx *ctx, int64_t shots, const uint64_t *err_x, c
 // added into the caller's.  Every node reads its per-call values from the device
 // descriptor, so a captured copy is replayed by changing only the prep node.
 static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int64_t shots, hipStream_t s,
-                               hipEvent_t *capture_ev = nullptr) {
+                               const RunWs &ws, bool capturing = false) {
     hipError_t e = mbbp::launch_run_prep(prep, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("prep launch: ") + hipGetErrorString(e));
     mbbp::SampleArgs sa{};
@@ -1089,34 +1102,77 @@ static mbbp_status run_enqueue(mbbp_ctx *ctx, const mbbp::RunPrepArgs &prep, int
     sa.part[1] = ctx->dp[1];
     sa.n = ctx->n;
     sa.shots = shots;
-    sa.err[0] = ctx->w_err[0]; sa.err[1] = ctx->w_err[1];
-    sa.syn[0] = ctx->w_syn[0]; sa.syn[1] = ctx->w_syn[1];
-    sa.desc = ctx->w_desc;
+    sa.err[0] = ws.err[0]; sa.err[1] = ws.err[1];
+    sa.syn[0] = ws.syn[0]; sa.syn[1] = ws.syn[1];
+    sa.desc = ws.desc;
     e = mbbp::launch_sample(sa, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("sample launch: ") + hipGetErrorString(e));
-    const uint64_t *sy[2] = {ctx->w_syn[0], ctx->w_syn[1]};
-    const float *pr[2] = {ctx->w_prior[0], ctx->w_prior[1]};
+    const uint64_t *sy[2] = {ws.syn[0], ws.syn[1]};
+    const float *pr[2] = {ws.prior[0], ws.prior[1]};
     float *ll[2] = {nullptr, nullptr};
     mbbp_status st;
-    if ((st = run_bp(ctx, 0, 2, shots, sy, pr, 0, ctx->cand, ctx->kstat, ll, true, s, nullptr, true, capture_ev)) !=
-        MBBP_OK)
+    if ((st = run_bp(ctx, 0, 2, shots, sy, pr, 0, ws.cand, ws.kstat, ll, true, s, nullptr, true, capturing,
+                     ws.queue)) != MBBP_OK)
         return st;
-    if ((st = run_select(ctx, 0, 2, shots, ctx->w_corr, ctx->w_conv, ctx->w_basis, ctx->w_counters, ctx->w_kmax,
-                         s)) != MBBP_OK)
+    if ((st = run_select(ctx, 0, 2, shots, ws.corr, ws.conv, ws.basis, ws.counters, ws.kmax, s, ws.cand,
+                         ws.kstat)) != MBBP_OK)
         return st;
     mbbp::FailArgs a{};
     a.part[0] = ctx->dp[0];
     a.part[1] = ctx->dp[1];
     a.shots = shots;
-    a.err[0] = ctx->w_err[0]; a.err[1] = ctx->w_err[1];
-    a.corr[0] = ctx->w_corr[0]; a.corr[1] = ctx->w_corr[1];
+    a.err[0] = ws.err[0]; a.err[1] = ws.err[1];
+    a.corr[0] = ws.corr[0]; a.corr[1] = ws.corr[1];
     a.fail = nullptr;
-    a.counters = ctx->w_counters;
-    a.kmax_shot = ctx->w_kmax;
+    a.counters = ws.counters;
+    a.kmax_shot = ws.kmax;
     e = mbbp::launch_fail(a, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("failure launch: ") + hipGetErrorString(e));
-    e = mbbp::launch_accumulate(ctx->w_counters, ctx->w_desc, MBBP_NUM_COUNTERS, s);
+    e = mbbp::launch_accumulate(ws.counters, ws.desc, MBBP_NUM_COUNTERS, s);
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("accumulate launch: ") + hipGetErrorString(e));
+    return MBBP_OK;
+}
+
+// The context's own run workspace (allocated by ensure_run_workspace).
+static RunWs ctx_ws(mbbp_ctx *ctx) {
+    RunWs w{};
+    for (int p = 0; p < 2; ++p) {
+        w.err[p] = ctx->w_err[p];
+        w.syn[p] = ctx->w_syn[p];
+        w.corr[p] = ctx->w_corr[p];
+        w.conv[p] = ctx->w_conv[p];
+        w.basis[p] = ctx->w_basis[p];
+        w.prior[p] = ctx->w_prior[p];
+        w.cand[p] = ctx->cand[p];
+        w.kstat[p] = ctx->kstat[p];
+    }
+    w.kmax = ctx->w_kmax;
+    w.counters = ctx->w_counters;
+    w.desc = ctx->w_desc;
+    w.queue = ctx->w_queue;
+    return w;
+}
+
+// Validation and the per-call descriptor of mbbp_run / mbbp_run_static.
+static mbbp_status run_prep_args(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
+                                 int64_t *counters, const RunWs &ws, mbbp::RunPrepArgs &prep) {
+    prep = mbbp::RunPrepArgs{};
+    prep.d.seed = seed;
+    prep.d.shot0 = shot0;
+    uint64_t t[3];
+    thresholds(p, ctx->noise, t);
+    prep.d.t1 = t[0]; prep.d.t2 = t[1]; prep.d.t3 = t[2];
+    prep.d.counters = counters;
+    prep.desc = ws.desc;
+    prep.prior0 = ws.prior[0];
+    prep.prior1 = ws.prior[1];
+    prep.n = ctx->n;
+    mbbp_status st = mbbp_prior_llr(ctx->noise, p, &prep.mu);
+    if (st != MBBP_OK) return st;
+    prep.kmax = ws.kmax;
+    prep.shots = shots;
+    prep.queue = ws.queue;
+    prep.counters = ws.counters;
     return MBBP_OK;
 }
 
@@ -1139,7 +1195,7 @@ static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &pre
         if (!ev) MBBP_HIP(hipEventCreate(&ev));
     MBBP_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
     mbbp::set_last_bp_kernel(nullptr);
-    mbbp_status st = run_enqueue(ctx, prep, shots, ctx->capture_stream, ctx->graph_ev);
+    mbbp_status st = run_enqueue(ctx, prep, shots, ctx->capture_stream, ctx_ws(ctx), true);
     g.bp_func = mbbp::last_bp_kernel();
     g.cfg = ctx->batched_cfg;
     hipGraph_t graph = nullptr;
@@ -1154,17 +1210,10 @@ static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &pre
     MBBP_HIP(hipGraphGetNodes(graph, nullptr, &count));
     std::vector<hipGraphNode_t> nodes(count);
     MBBP_HIP(hipGraphGetNodes(graph, nodes.data(), &count));
-    int n_ev = 0;
+    hipGraphNode_t bp = nullptr;
     for (hipGraphNode_t nd : nodes) {
         hipGraphNodeType ty;
         MBBP_HIP(hipGraphNodeGetType(nd, &ty));
-        if (ty == hipGraphNodeTypeEventRecord) {
-            hipEvent_t ev = nullptr;
-            MBBP_HIP(hipGraphEventRecordNodeGetEvent(nd, &ev));
-            for (int k = 0; k < 2; ++k)
-                if (ev == ctx->graph_ev[k]) g.ev_node[k] = nd;
-            ++n_ev;
-        }
         if (ty != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams kp;
         MBBP_HIP(hipGraphKernelNodeGetParams(nd, &kp));
@@ -1172,10 +1221,26 @@ static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &pre
             g.prep = nd;
             g.prep_params = kp;
         }
+        if (kp.func == g.bp_func) bp = nd;
     }
     if (!g.prep) return fail(MBBP_EDEVICE, "captured graph has no preparation node");
-    if (n_ev != 2 || !g.ev_node[0] || !g.ev_node[1])
-        return fail(MBBP_EDEVICE, "captured graph lacks the BP timing event nodes");
+    if (!bp) return fail(MBBP_EDEVICE, "captured graph has no BP kernel node");
+    // event record nodes around the BP kernel node: pred -> ev0 -> bp -> ev1 -> succ
+    {
+        size_t nd = 0, ns = 0;
+        MBBP_HIP(hipGraphNodeGetDependencies(bp, nullptr, &nd));
+        std::vector<hipGraphNode_t> pred(nd);
+        if (nd) MBBP_HIP(hipGraphNodeGetDependencies(bp, pred.data(), &nd));
+        MBBP_HIP(hipGraphNodeGetDependentNodes(bp, nullptr, &ns));
+        std::vector<hipGraphNode_t> succ(ns);
+        if (ns) MBBP_HIP(hipGraphNodeGetDependentNodes(bp, succ.data(), &ns));
+        for (hipGraphNode_t p : pred) MBBP_HIP(hipGraphRemoveDependencies(graph, &p, &bp, 1));
+        for (hipGraphNode_t q : succ) MBBP_HIP(hipGraphRemoveDependencies(graph, &bp, &q, 1));
+        MBBP_HIP(hipGraphAddEventRecordNode(&g.ev_node[0], graph, pred.data(), pred.size(), ctx->graph_ev[0]));
+        MBBP_HIP(hipGraphAddDependencies(graph, &g.ev_node[0], &bp, 1));
+        MBBP_HIP(hipGraphAddEventRecordNode(&g.ev_node[1], graph, &bp, 1, ctx->graph_ev[1]));
+        for (hipGraphNode_t q : succ) MBBP_HIP(hipGraphAddDependencies(graph, &g.ev_node[1], &q, 1));
+    }
     MBBP_HIP(hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
     return MBBP_OK;
 }
@@ -1183,29 +1248,15 @@ static mbbp_status capture_run_graph(mbbp_ctx *ctx, const mbbp::RunPrepArgs &pre
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, int64_t *counters,
                      void *hip_stream) {
     if (!ctx) return fail(MBBP_EINVAL, "null ctx");
-    if (!(p > 0.0 && p < 1.5) || p > 1.0) return fail(MBBP_EINVAL, "p must be in (0, 1]");
+    if (!(p > 0.0 && p <= 1.0)) return fail(MBBP_EINVAL, "p must be in (0, 1]");
     if (shots < 1 || shots > ctx->params.max_batch || shot0 < 0) return fail(MBBP_EINVAL, "shots out of range");
     if (!counters) return fail(MBBP_EINVAL, "null counters");
     mbbp_status st = ensure_run_workspace(ctx);
     if (st != MBBP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     mbbp::RunPrepArgs prep{};
-    prep.d.seed = seed;
-    prep.d.shot0 = shot0;
-    uint64_t t[3];
-    thresholds(p, ctx->noise, t);
-    prep.d.t1 = t[0]; prep.d.t2 = t[1]; prep.d.t3 = t[2];
-    prep.d.counters = counters;
-    prep.desc = ctx->w_desc;
-    prep.prior0 = ctx->w_prior[0];
-    prep.prior1 = ctx->w_prior[1];
-    prep.n = ctx->n;
-    if ((st = mbbp_prior_llr(ctx->noise, p, &prep.mu)) != MBBP_OK) return st;
-    prep.kmax = ctx->w_kmax;
-    prep.shots = shots;
-    prep.queue = ctx->w_queue;
-    prep.counters = ctx->w_counters;
-    if (!ctx->use_graph) return run_enqueue(ctx, prep, shots, s);
+    if ((st = run_prep_args(ctx, seed, p, shot0, shots, counters, ctx_ws(ctx), prep)) != MBBP_OK) return st;
+    if (!ctx->use_graph) return run_enqueue(ctx, prep, shots, s, ctx_ws(ctx));
     auto it = ctx->graphs.find(shots);
     if (it != ctx->graphs.end() && !same_config(it->second.cfg, ctx->batched_cfg)) {
         // captured with another launch shape: capture again

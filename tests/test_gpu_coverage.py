@@ -88,35 +88,49 @@ def mcnemar_p(b, c):
 # ------------------------------------------------------------------ sum-product on codes with cycles
 
 @pytest.mark.parametrize("key,p,shots", [("bb72_L4_T20", 0.05, 2000), ("bb144_L16_T50", 0.06, 600)])
-@pytest.mark.parametrize("schedule", [0, 1])
-def test_spa_codes_short_horizon_fp64(pk, key, p, shots, schedule):
-    """Sum-product (Section II-B's product-sum rule) on the codes' representations,
-    fixed horizon T = 5: every GPU posterior within 1e-4 * max(1, |LLR|) of the FP64
-    oracle, hard decisions, iteration counts and convergence equal except on
-    tie-prone instances (FP64 margin < 1e-3), whose number is printed."""
+@pytest.mark.parametrize("rule,schedule", [(1, 0), (1, 1), (0, 1)])
+def test_short_horizon_fp64(pk, key, p, shots, rule, schedule):
+    """Sum-product (Section II-B's product-sum rule) and serial min-sum on the codes'
+    representations, fixed horizon T = 5, against the FP64 oracle: hard decisions,
+    iteration counts and convergence equal except on tie-prone instances (FP64
+    margin < 1e-3, counted); posteriors within 1e-4 * max(1, |LLR|).  In the serial
+    schedule messages grow to hundreds within the horizon and a posterior of order 1
+    is a sum of such terms, so single-precision rounding is relative to the
+    instance's largest posterior: there the bound is 1e-4 * max(1, max_j |LLR_j| of
+    the instance), and the entries beyond the per-entry bound are counted, together
+    with those of the single-precision oracle (a different evaluation of the same
+    rule) as a reference for what FP32 gives."""
     wl = WORKLOADS[key]
     code = wl.code()
-    dec, bx, bz = make_decoder(pk, code, wl, T=5, max_batch=shots, rule=pk.SPA, fixed_T=True,
-                               schedule=schedule)
-    say(f"spa {key} schedule={schedule} p={p} shots={shots} T=5 vs FP64")
+    dec, bx, bz = make_decoder(pk, code, wl, T=5, max_batch=shots, rule=rule, fixed_T=True, schedule=schedule)
+    say(f"{('NMS', 'SPA')[rule]} {key} schedule={schedule} p={p} shots={shots} T=5 vs FP64")
     ex, ez, sx, sz = dec.sample(wl.seed, p, 321, shots)
     mu = f32(oracle.prior_llr(p))
     prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
     for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
         cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
         torch.cuda.synchronize()
-        ref = oracle_decode_par(h, bp, rows, words(syn), np.full(code.n, mu), 5, schedule=schedule,
-                                rule=oracle.SPA, fixed_T=True, want_llr=True)
+        kw = dict(schedule=schedule, rule=rule, alpha=wl.alpha, fixed_T=True, want_llr=True)
+        ref = oracle_decode_par(h, bp, rows, words(syn), np.full(code.n, mu), 5, **kw)
+        ref32 = oracle_decode_par(h, bp, rows, words(syn), np.full(code.n, mu), 5, precision="f32", **kw)
         ks = kstat.cpu().numpy().view(np.uint16)
         K, conv = (ks & 0x7FFF).astype(np.int32), (ks >> 15).astype(bool)
         same = (words(cand) == ref.cand).all(axis=-1) & (K == ref.K) & (conv == ref.conv)
         tie = tie_shots(ref.margin)
         got = llr.cpu().numpy().astype(np.float64)
         err = np.abs(got - ref.llr) / np.maximum(1.0, np.abs(ref.llr))
-        say(f"  part {part}: differing instances {int((~same).sum())} of {same.size} "
-            f"(tie-prone {int(tie.sum())}), max relative LLR error {err.max():.2e}")
+        err32 = np.abs(ref32.llr - ref.llr) / np.maximum(1.0, np.abs(ref.llr))
+        scale = np.maximum(1.0, np.abs(ref.llr).max(axis=-1, keepdims=True))
+        err_inst = np.abs(got - ref.llr) / scale
+        say(f"  part {part}: differing instances {int((~same).sum())} of {same.size} (tie-prone {int(tie.sum())}); "
+            f"max relative LLR error {err.max():.2e} ({int((err > 1e-4).sum())} entries beyond 1e-4; "
+            f"single-precision oracle {err32.max():.2e}, {int((err32 > 1e-4).sum())} entries), "
+            f"relative to the instance's largest posterior {err_inst.max():.2e}")
         assert not (~same & ~tie).any(), "decision differs from FP64 on a non-tie instance"
-        assert err.max() <= 1e-4
+        if schedule == 0:
+            assert err.max() <= 1e-4
+        else:
+            assert err_inst.max() <= 1e-4
     dec.close()
 
 
