@@ -201,6 +201,21 @@ enum {
 mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
                      int64_t *counters, void *hip_stream);
 
+/* mbbp_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same path
+ * and results as mbbp_run, launched directly on hip_stream (no graph, no event,
+ * no hipMalloc / hipFree), with every intermediate buffer in one static device
+ * array of 64 MiB that each GPU holds until the process ends.  `shots` is bounded
+ * by that array, not by max_batch: per shot 8 (W + Ws) + 8 W + 10 + 8 L W + 2 L
+ * bytes for each part (W = ceil(n/64), Ws = ceil(m/64) of the part's matrix, L
+ * representations), plus 4, in 256-byte aligned pieces; a larger batch is
+ * MBBP_EINVAL and the message names the largest that fits.  The decoder's device
+ * must be current.  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (two streams, two threads, two decoders) race and give wrong
+ * counters; serialise them.  counters as in mbbp_run (accumulated into). */
+mbbp_status mbbp_run_static(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
+                            int64_t *counters, void *hip_stream);
+
 /* Launch configuration of the BP kernel (the autotuner's search space).
  * form: 0 = mbbp_decode / mbbp_decode_detail, 1 = mbbp_decode_batched / mbbp_run.
  * lanes_per_instance: 64 (one instance per wavefront; other values: MBBP_EUNSUPPORTED);

@@ -356,6 +356,18 @@ class Decoder:
                                                 _stream(stream)), "mbbp_wbp_backward")
         return grad_alpha, grad_beta
 
+    def run_static(self, seed: int, p: float, shot0: int, shots: int, counters=None, stream=None):
+        """run() through mbbp_run_static: no device allocation inside the library (its
+        buffers live in one static device array; `counters` must be given by callers
+        that cannot allocate)."""
+        torch = _torch()
+        if counters is None:
+            counters = torch.zeros(NUM_COUNTERS, dtype=torch.int64, device="cuda")
+        _need(counters, "counters", (NUM_COUNTERS,), torch.int64)
+        _lib.check(_lib.lib().mbbp_run_static(self._ctx, int(seed) & (2**64 - 1), float(p), int(shot0),
+                                              int(shots), _ptr(counters), _stream(stream)), "mbbp_run_static")
+        return counters
+
     def run(self, seed: int, p: float, shot0: int, shots: int, counters=None, stream=None):
         torch = _torch()
         if counters is None:

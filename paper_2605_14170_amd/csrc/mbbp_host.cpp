@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,17 @@
 namespace {
 
 thread_local std::string g_last_error;
+
+// Scratch of the allocation-free entry point mbbp_run_static: every buffer of the
+// whole path (noise, syndromes, candidates, decisions, counters, work queue) is
+// carved from this array, which each GPU holds from module load to process end.
+// Host code never passes its name to a kernel: it is a host-side stand-in, and
+// the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
 
 mbbp_status fail(mbbp_status st, const std::string &msg) {
     g_last_error = msg;
@@ -476,6 +488,7 @@ struct mbbp_ctx {
     bool use_graph = true;  // mbbp_run replays a captured graph
     hipEvent_t graph_ev[2] = {nullptr, nullptr};  // events of the captured record nodes (untimed replays)
     bool per_basis = false;  // mbbp_decode: one BP launch per (part, representation)
+    unsigned char *scratch_dev = nullptr;  // this device's copy of the static scratch array
     const int32_t *rep_ids = nullptr;  // device [2L]: p * L + l in order (single-pair launches)
     // BP kernel event timing
     bool timing = false;
@@ -901,6 +914,20 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
         hipDeviceProp_t prop;
         MBBP_HIP(hipGetDeviceProperties(&prop, c->device));
         c->cu_count = prop.multiProcessorCount;
+        // device address of the static scratch array on this device (taken once per
+        // device, with the device current)
+        {
+            if (c->device < 0 || c->device >= kMaxDevices) return fail(MBBP_EUNSUPPORTED, "device index too large");
+            std::lock_guard<std::mutex> lk(g_scratch_mu);
+            if (!g_scratch_ptr[c->device]) {
+                void *ptr = nullptr;
+                hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+                if (e != hipSuccess || !ptr)
+                    return fail(MBBP_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+                g_scratch_ptr[c->device] = ptr;
+            }
+            c->scratch_dev = static_cast<unsigned char *>(g_scratch_ptr[c->device]);
+        }
         // part X (H_Z) tests residuals with H_Z and L_Z; part Z with H_X and L_X
         if ((st = upload_part(c.get(), 0, c->LZ)) != MBBP_OK) return st;
         if ((st = upload_part(c.get(), 1, c->LX)) != MBBP_OK) return st;
@@ -1291,6 +1318,67 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
     MBBP_HIP(hipGraphLaunch(g.exec, s));
     if (ctx->timing) ctx->events.push_back({ev[0], ev[1]});
     return MBBP_OK;
+}
+
+// Carves the run buffers for `shots` out of the scratch array at `base`; returns
+// the bytes used (256-byte aligned pieces).  With base == nullptr only sizes.
+static size_t carve_ws(const mbbp_ctx *ctx, int64_t shots, unsigned char *base, RunWs &w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> unsigned char * {
+        unsigned char *p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    const size_t S = (size_t)shots;
+    w.desc = reinterpret_cast<mbbp::RunDesc *>(take(sizeof(mbbp::RunDesc)));
+    w.counters = reinterpret_cast<int64_t *>(take(8 * MBBP_NUM_COUNTERS));
+    w.queue = reinterpret_cast<unsigned long long *>(take(8));
+    w.kmax = reinterpret_cast<int *>(take(4 * S));
+    for (int p = 0; p < 2; ++p) {
+        const size_t W = ctx->dp[p].W, Ws = ctx->dp[p].Ws, L = ctx->dp[p].L;
+        w.prior[p] = reinterpret_cast<float *>(take(4 * (size_t)ctx->n));
+        w.err[p] = reinterpret_cast<uint64_t *>(take(8 * S * W));
+        w.syn[p] = reinterpret_cast<uint64_t *>(take(8 * S * Ws));
+        w.corr[p] = reinterpret_cast<uint64_t *>(take(8 * S * W));
+        w.conv[p] = reinterpret_cast<uint64_t *>(take(8 * S));
+        w.basis[p] = reinterpret_cast<int16_t *>(take(2 * S));
+        w.cand[p] = reinterpret_cast<uint64_t *>(take(8 * S * L * W));
+        w.kstat[p] = reinterpret_cast<uint16_t *>(take(2 * S * L));
+    }
+    return off;
+}
+
+mbbp_status mbbp_run_static(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots, int64_t *counters,
+                            void *hip_stream) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (!(p > 0.0 && p <= 1.0)) return fail(MBBP_EINVAL, "p must be in (0, 1]");
+    if (shots < 1 || shot0 < 0) return fail(MBBP_EINVAL, "shots out of range");
+    if (!counters) return fail(MBBP_EINVAL, "null counters");
+    if (!ctx->scratch_dev) return fail(MBBP_EDEVICE, "no scratch address for this device");
+    RunWs ws{};
+    if (carve_ws(ctx, shots, nullptr, ws) > kScratchBytes) {
+        int64_t lo = 0, hi = shots;  // largest batch that fits, for the message
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (carve_ws(ctx, mid, nullptr, ws) <= kScratchBytes) lo = mid;
+            else hi = mid - 1;
+        }
+        return fail(MBBP_EINVAL, "shots = " + std::to_string(shots) + " exceed the static scratch of " +
+                                     std::to_string(kScratchBytes >> 20) + " MiB (at most " + std::to_string(lo) +
+                                     " shots for this decoder)");
+    }
+    int dev = -1;
+    MBBP_HIP(hipGetDevice(&dev));
+    if (dev != ctx->device) return fail(MBBP_EINVAL, "the decoder's device is not the current device");
+    carve_ws(ctx, shots, ctx->scratch_dev, ws);
+    mbbp::RunPrepArgs prep{};
+    mbbp_status st = run_prep_args(ctx, seed, p, shot0, shots, counters, ws, prep);
+    if (st != MBBP_OK) return st;
+    const bool timing = ctx->timing;  // no event objects are made here
+    ctx->timing = false;
+    st = run_enqueue(ctx, prep, shots, static_cast<hipStream_t>(hip_stream), ws);
+    ctx->timing = timing;
+    return st;
 }
 
 mbbp_status mbbp_run_graph_config(mbbp_ctx *ctx, int64_t shots, mbbp_launch_config *cfg) {
