@@ -30,13 +30,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU lane-operations per edge-message update of normalized min-sum
-# (two-minimum tracking 2, sign parity 1, minimum test and select 2, sign apply 1,
-# per-check scaling and clamp ~0.7, posterior and message sums 2, syndrome parity 1,
-# decision ~0.3).
-OPS_PER_EDGE_UPDATE = 10.0
+# Algorithmic VALU lane-operations per edge-message update of normalized min-sum,
+# flooding: v->c exclusion sum 2, sign extract and parity 2, two-minimum tracking 5,
+# output select, scaling and sign 4, posterior accumulation 1 (the decision and
+# parity bits are bit-packed, under 1).
+OPS_PER_EDGE_UPDATE = 14.0
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed 32-bit VALU lane-ops)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS: 256 CUs x 128 B/clk x 2.4 GHz; algorithmic LDS bytes per edge update: one
+# 4-byte write and one 4-byte read of the exchanged message
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
+LDS_BYTES_PER_EDGE_UPDATE = 8.0
+# HBM3E
+HBM_PEAK_GBPS = 8000.0
 
 
 def parse():
@@ -46,13 +52,20 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bb144_L16_T50")
     ap.add_argument("--shots", type=int, default=None, help="shots per error rate per step")
-    ap.add_argument("--form", choices=["batched", "plain"], default="batched")
+    ap.add_argument("--form", choices=["batched", "plain", "per-basis"], default="batched",
+                    help="batched: mbbp_run (persistent launch, graph replay); plain: sample + mbbp_decode + "
+                         "failures; per-basis: the same with one BP launch per (part, representation)")
+    ap.add_argument("--rule", choices=["nms", "spa"], default="nms")
+    ap.add_argument("--schedule", choices=["flooding", "layered"], default="flooding")
+    ap.add_argument("--per-shot-priors", action="store_true",
+                    help="non-uniform soft priors per shot and qubit (resident in HBM before the timed region), "
+                         "decoded by mbbp_decode_batched")
     ap.add_argument("--lpi", type=int, default=0, help="lanes per BP instance (0 = library choice)")
     ap.add_argument("--wpb", type=int, default=4, help="waves per block (with --lpi)")
     ap.add_argument("--chunk", type=int, default=8, help="shots per work item (with --lpi)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-shots", type=int, default=60000, help="oracle sample: shots per error rate")
-    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = every host core)")
     ap.add_argument("--train-steps", type=int, default=2000, help="weighted workload: Adam steps")
     ap.add_argument("--train-batch", type=int, default=4096, help="weighted workload: shots per Adam step")
     ap.add_argument("--lr", type=float, default=1e-3, help="weighted workload: Adam learning rate")
@@ -103,36 +116,42 @@ def recorded_traffic(workload, shots_per_launch):
         return None
 
 
-def build_decoder(pk, wl, code, max_batch, T=None, rule=0):
+def build_decoder(pk, wl, code, max_batch, T=None, rule=0, schedule=0):
     from workloads.perms import check_permutations
     perms = lambda h: check_permutations(h.shape[0], max(wl.L, 8), wl.perm_seed)  # noqa: E731
     bx = pk.build_bases(code.hx, wl.basis_mode, wl.L, perms(code.hx))
     bz = pk.build_bases(code.hz, wl.basis_mode, wl.L, perms(code.hz))
     dec = pk.Decoder(code.hx, code.hz, bx, bz, wl.T if T is None else T, alpha=wl.alpha, rule=rule,
-                     max_batch=max_batch)
+                     schedule=schedule, max_batch=max_batch)
     return dec, bx, bz
 
 
-def cpu_baseline(wl, code, bx, bz, shots_per_p, threads):
+def cpu_baseline(wl, code, bx, bz, shots_per_p, threads, shot0s, rule=0, schedule=0):
     """The oracle as it stands (FP64, single-threaded per call) on `threads` host
-    threads over disjoint shot ranges of the same workload."""
+    threads over disjoint shot ranges: at each p the first `shots_per_p` shots the
+    GPU decodes in its first timed step (the same shot indices, so the same noise).
+    Its failures give the oracle's logical error rate beside the GPU's."""
     import oracle
-    chunk = max(1, shots_per_p // threads)
+    chunk = max(1, -(-shots_per_p // threads))
     jobs = []
-    for p in wl.ps:
+    for i, p in enumerate(wl.ps):
         for start in range(0, shots_per_p, chunk):
-            jobs.append((p, start, min(chunk, shots_per_p - start)))
+            jobs.append((i, p, shot0s[i] + start, min(chunk, shots_per_p - start)))
     t0 = time.perf_counter()
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        res = list(ex.map(lambda j: oracle.run(code, bx, bz, wl.seed, j[0], 10**12 + j[1], j[2], wl.T, wl.alpha),
-                          jobs))
+        res = list(ex.map(lambda j: oracle.run(code, bx, bz, wl.seed, j[1], j[2], j[3], wl.T, wl.alpha,
+                                               schedule=schedule, rule=rule), jobs))
     dt = time.perf_counter() - t0
     shots = sum(r.shots for r in res)
     edges = sum(r.edge_updates for r in res)
+    per_p = {}
+    for i, p in enumerate(wl.ps):
+        f = sum(r.fails for j, r in zip(jobs, res) if j[0] == i)
+        per_p[str(p)] = dict(shots=shots_per_p, fails=f, ler=f / shots_per_p, ler_95=wilson(f, shots_per_p))
     return dict(value=shots / dt, unit="shots/s", cores=threads, kind="oracle",
-                edge_updates_per_s=edges / dt, seconds=dt,
-                sample=f"{shots_per_p} shots at each p in {list(wl.ps)} ({shots} shots), FP64 oracle, "
-                       f"{threads} threads over disjoint shot ranges")
+                edge_updates_per_s=edges / dt, seconds=dt, per_p=per_p,
+                sample=f"the first {shots_per_p} shots of the first timed step at each p in {list(wl.ps)} "
+                       f"({shots} shots), FP64 oracle, {threads} threads over disjoint shot ranges")
 
 
 def wilson(k, n, z=1.959963984540054):
@@ -176,22 +195,18 @@ def paper_ler_main(args, wl, code):
 
 
 def partition_bases(pk, h, k, seed, mode, count=None):
-    """Bases of partition k: the maximal subtrees of root order pi_k (Algorithm 2,
-    pi_0 the identity), one representation [H; H_t] per subtree t with H_t its rows in
-    acceptance order (tree), or |H_t| distinct rows of H drawn at random (random,
-    the matched random augmentation of the paper's Table II)."""
+    """Bases of partition k: the maximal subtrees of root order pi_k (the library's
+    Algorithm 2, pi_0 the identity), one representation [H; H_t] per subtree t
+    (tree), or matched random rows (random, the control of the paper's Table II)."""
+    from workloads.partitions import matched_random_bases, tree_bases
     from workloads.perms import check_permutations
     m = h.shape[0]
     perm = check_permutations(m, k + 1, seed)[k]
     cs, order, ns = pk.subtrees(h, perm)
-    rng = np.random.Generator(np.random.PCG64([int(seed), 7919, int(k)]))
     subs = [[int(c) for c in order if cs[c] == t] for t in range(1, ns + 1)]
-    bp, rows = [0], []
-    for i in range(ns if count is None else count):
-        sub = subs[i % ns]
-        rows += sub if mode == "tree" else [int(x) for x in rng.choice(m, len(sub), replace=False)]
-        bp.append(len(rows))
-    return np.asarray(bp, np.int32), np.asarray(rows, np.int32)
+    if mode == "tree":
+        return tree_bases(subs, count)
+    return matched_random_bases(subs, m, seed, k, count)
 
 
 def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
@@ -335,6 +350,29 @@ def weighted_main(args, wl, code):
     print(json.dumps(line), flush=True)
 
 
+def algorithmic_hbm_bytes_per_shot(code):
+    """Bytes a shot must move to or from HBM when its errors are generated in the
+    kernel: both corrections, both convergence masks, both chosen representations
+    and the failure flag (about 69 B for n = 144)."""
+    W = (code.n + 63) // 64
+    return 2 * W * 8 + 2 * 8 + 2 * 2 + 1
+
+
+def soft_priors(torch, code, p, shots, seed):
+    """Per-shot, per-qubit priors of a non-uniform channel (inputs of the per-shot
+    prior workload): flip probability q of each (shot, qubit, part) drawn
+    log-uniformly in [p/3, 4p/3], prior log((1 - q) / q); generated on the GPU before
+    the timed region."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    out = []
+    for _ in range(2):
+        u = torch.rand((shots, code.n), generator=g, device="cuda", dtype=torch.float64)
+        q = (p / 3.0) * torch.exp(u * np.log(4.0))
+        out.append(torch.log((1.0 - q) / q).to(torch.float32).contiguous())
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -364,26 +402,36 @@ def main():
     if args.paper_ler:
         return paper_ler_main(args, wl, code)
     shots = args.shots or wl.shots
+    rule = pk.SPA if args.rule == "spa" else pk.NMS
+    schedule = pk.LAYERED if args.schedule == "layered" else pk.FLOODING
     torch.cuda.set_device(0)
-    dec, bx, bz = build_decoder(pk, wl, code, shots)
+    dec, bx, bz = build_decoder(pk, wl, code, shots, rule=rule, schedule=schedule)
     if args.lpi:
         for form in (0, 1):
             dec.set_config(form, args.lpi, args.wpb, args.chunk, 0)
+    form = "pps" if args.per_shot_priors else args.form
+    if form == "per-basis":
+        dec.set_per_basis(True)
     ps = list(wl.ps)
     stream = torch.cuda.current_stream()
+    pri = {p: soft_priors(torch, code, p, shots, 1000 + i) for i, p in enumerate(ps)} if form == "pps" else None
+    unif = {p: torch.full((code.n,), pk.prior_llr(p), dtype=torch.float32, device="cuda") for p in ps}
+    base_of = lambda k, i: (k * len(ps) + i) * shots  # noqa: E731  fresh shot indices per step and p
 
     def step(k, counters):
         for i, p in enumerate(ps):
-            base = (k * len(ps) + i) * shots
-            if args.form == "batched":
+            base = base_of(k, i)
+            if form == "batched":
                 dec.run(wl.seed, p, base, shots, counters[i], stream)
-            else:
-                ex, ez, sx, sz = dec.sample(wl.seed, p, base, shots, stream)
-                prior = torch.full((code.n,), pk.prior_llr(p), dtype=torch.float32, device="cuda")
-                out = dec.decode(sx, sz, prior, prior, stream)
-                dec.failures(ex, ez, out["corr_x"], out["corr_z"], stream)
+                continue
+            ex, ez, sx, sz = dec.sample(wl.seed, p, base, shots, stream)
+            px, pz = pri[p] if form == "pps" else (unif[p], unif[p])
+            out = (dec.decode_batched if form == "pps" else dec.decode)(sx, sz, px, pz, stream)
+            f = dec.failures(ex, ez, out["corr_x"], out["corr_z"], stream)
+            counters[i, pk.CNT_FAIL] += (f != 0).sum()
 
-    print(f"# workload {wl.key}: {wl.description}; shots/p/step {shots}", file=sys.stderr, flush=True)
+    print(f"# workload {wl.key}: {wl.description}; shots/p/step {shots}; form {form}, rule {args.rule}, "
+          f"schedule {args.schedule}", file=sys.stderr, flush=True)
     warm = torch.zeros((len(ps), pk.NUM_COUNTERS), dtype=torch.int64, device="cuda")
     for k in range(args.warmup):
         step(10_000 + k, warm)
@@ -402,45 +450,83 @@ def main():
     bp_ms, bp_launches = dec.bp_time(reset=True)
     c = counters.cpu().numpy()
     total_shots = shots * len(ps) * args.steps
-    edges = int(c[:, pk.CNT_EDGE_UPDATES].sum())
+    n_per_p = shots * args.steps
+    edges = int(c[:, pk.CNT_EDGE_UPDATES].sum()) if form == "batched" else None
     ms_per_step = dt * 1e3 / args.steps
     value = total_shots / dt
-    per_p = {str(p): dict(ler=float(c[i, pk.CNT_FAIL]) / (shots * args.steps),
-                          mean_kmax=float(c[i, pk.CNT_SUM_KMAX]) / (shots * args.steps),
-                          mean_k=float(c[i, pk.CNT_SUM_K]) / (shots * args.steps * 2 * wl.L),
-                          noconv_frac=float(c[i, pk.CNT_NOCONV]) / (shots * args.steps * 2))
-             for i, p in enumerate(ps)}
+    per_p = {}
+    for i, p in enumerate(ps):
+        f = int(c[i, pk.CNT_FAIL])
+        d = dict(fails=f, ler=f / n_per_p, ler_95=wilson(f, n_per_p))
+        if form == "batched":
+            d.update(mean_kmax=float(c[i, pk.CNT_SUM_KMAX]) / n_per_p,
+                     mean_k=float(c[i, pk.CNT_SUM_K]) / (n_per_p * 2 * wl.L),
+                     noconv_frac=float(c[i, pk.CNT_NOCONV]) / (n_per_p * 2),
+                     ties_frac=float(c[i, pk.CNT_TIES]) / (n_per_p * 2))
+        per_p[str(p)] = d
     print(f"# timed {args.steps} steps in {dt:.3f} s; BP kernel {bp_ms:.1f} ms over {bp_launches} launches",
           file=sys.stderr, flush=True)
+    roofline = None
+    launches_per_step = bp_launches / max(1, args.steps)
     bp_avg_s = bp_ms / 1e3 / max(1, bp_launches)
-    edges_per_launch = edges / max(1, bp_launches)
-    achieved = edges_per_launch * OPS_PER_EDGE_UPDATE / bp_avg_s / 1e12 if bp_launches else None
-    roofline = dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="T lane-op/s",
-                    frac=(achieved / VALU_PEAK_TOPS) if achieved else None, traffic_unit="B per launch",
-                    traffic=recorded_traffic(wl.key, shots) if args.form == "batched" else None,
-                    kernel="bp_kernel", avg_launch_ms=bp_avg_s * 1e3,
-                    edge_updates_per_launch=edges_per_launch,
-                    ops_per_edge_update=OPS_PER_EDGE_UPDATE)
+    if edges is not None and bp_launches:
+        edges_per_launch = edges / bp_launches
+        achieved = edges_per_launch * OPS_PER_EDGE_UPDATE / bp_avg_s / 1e12
+        traffic = recorded_traffic(wl.key, shots) if (args.form == "batched" and rule == pk.NMS and
+                                                       schedule == pk.FLOODING) else None
+        alg_hbm = algorithmic_hbm_bytes_per_shot(code) * shots
+        lds_tbps = edges_per_launch * LDS_BYTES_PER_EDGE_UPDATE / bp_avg_s / 1e12
+        roofline = dict(
+            bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="T lane-op/s", frac=achieved / VALU_PEAK_TOPS,
+            traffic=traffic, traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE, "
+                                          "recorded for this kernel source and launch size, else null)",
+            kernel="BP kernel", avg_launch_ms=bp_avg_s * 1e3, launches=bp_launches,
+            edge_updates_per_launch=edges_per_launch, ops_per_edge_update=OPS_PER_EDGE_UPDATE,
+            edge_updates_per_s_in_kernel=edges_per_launch / bp_avg_s,
+            lds=dict(algorithmic_bytes_per_edge_update=LDS_BYTES_PER_EDGE_UPDATE, achieved_TBps=lds_tbps,
+                     peak_TBps=LDS_PEAK_TBPS, frac=lds_tbps / LDS_PEAK_TBPS),
+            hbm=dict(algorithmic_bytes_per_launch=alg_hbm,
+                     algorithmic_bytes_per_shot=algorithmic_hbm_bytes_per_shot(code),
+                     achieved_GBps=(traffic / bp_avg_s / 1e9) if traffic else None, peak_GBps=HBM_PEAK_GBPS,
+                     frac=(traffic / bp_avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None,
+                     traffic_over_algorithmic=(traffic / alg_hbm) if traffic else None))
     line = dict(metric="MBBP-LD decoded shots/s and BP edge-msg updates/s at matched logical error rate",
                 value=value, unit="shots/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                 ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype="f32", data="synthetic",
                 config=dict(workload=wl.key, code=code.name, n=code.n, L=wl.L, T=wl.T, alpha=wl.alpha,
-                            ps=ps, shots_per_p=shots, schedule="flooding", rule="normalized min-sum",
-                            form=args.form, basis_mode=wl.basis_mode,
-                            launch=dec.get_config(1 if args.form == "batched" else 0)),
-                edge_updates_per_s=edges / dt, per_p=per_p, roofline=roofline)
+                            ps=ps, shots_per_p=shots, schedule=args.schedule,
+                            rule="sum-product" if rule == pk.SPA else "normalized min-sum",
+                            form={"batched": "batched (mbbp_run, persistent launch, graph replay)",
+                                  "plain": "plain (mbbp_sample + mbbp_decode + mbbp_failures)",
+                                  "per-basis": "plain with one BP launch per (part, representation)",
+                                  "pps": "per-shot priors (mbbp_sample + mbbp_decode_batched + mbbp_failures)"}[form],
+                            basis_mode=wl.basis_mode, bp_launches_per_step=launches_per_step,
+                            launch=dec.get_config(1 if form in ("batched", "pps") else 0)),
+                edge_updates_per_s=(edges / dt) if edges is not None else None, per_p=per_p, roofline=roofline)
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        threads = args.cpu_threads or len(os.sched_getaffinity(0))
         print(f"# cpu baseline: oracle on {threads} threads", file=sys.stderr, flush=True)
         import oracle
+        from workloads.perms import check_permutations
         obx = oracle.build_bases(code.hx, wl.basis_mode, wl.L,
-                                 __import__("workloads").check_permutations(code.hx.shape[0], max(wl.L, 8),
-                                                                             wl.perm_seed))
+                                 check_permutations(code.hx.shape[0], max(wl.L, 8), wl.perm_seed))
         obz = oracle.build_bases(code.hz, wl.basis_mode, wl.L,
-                                 __import__("workloads").check_permutations(code.hz.shape[0], max(wl.L, 8),
-                                                                             wl.perm_seed))
-        line["cpu_baseline"] = cpu_baseline(wl, code, obx, obz, args.cpu_shots, threads)
+                                 check_permutations(code.hz.shape[0], max(wl.L, 8), wl.perm_seed))
+        n_cpu = min(args.cpu_shots, shots)
+        cb = cpu_baseline(wl, code, obx, obz, n_cpu, threads, [base_of(0, i) for i in range(len(ps))],
+                          rule=int(rule), schedule=int(schedule))
+        line["cpu_baseline"] = cb
+        # matched logical error rate: the GPU decodes the oracle's very shots again
+        # (outside the timed region) and both failure counts are compared on them
+        for i, p in enumerate(ps):
+            d, o = per_p[str(p)], cb["per_p"][str(p)]
+            g = dec.run(wl.seed, p, base_of(0, i), n_cpu).cpu().numpy()
+            gf = int(g[pk.CNT_FAIL])
+            d["oracle_sample"] = dict(shots=n_cpu, oracle_fails=o["fails"], oracle_ler=o["ler"],
+                                      oracle_ler_95=o["ler_95"], gpu_fails=gf, gpu_ler=gf / n_cpu,
+                                      gpu_ler_95=wilson(gf, n_cpu))
+            d["gpu_ler_in_oracle_95"] = o["ler_95"][0] <= d["ler"] <= o["ler_95"][1]
     dec.close()
     print(json.dumps(line), flush=True)
 
