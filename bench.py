@@ -81,6 +81,7 @@ def parse():
                     help="--paper-ler: the workload's bases, or per partition (the maximal subtrees of one "
                          "root order, Algorithm 2) its subtree rows (tree) or as many random rows (random)")
     ap.add_argument("--ler-partitions", type=int, default=1, help="--paper-ler with tree/random: partitions")
+    ap.add_argument("--serial-lanes", type=int, default=0, help="serial schedule: shots per wavefront (0 = library)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -215,9 +216,14 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
     dec = pk.Decoder(code.hx, code.hz, bx, bz, 100, schedule=pk.LAYERED, alpha=0.875, select=pk.FWS,
                      max_batch=batch)
     dec.set_noise(pk.X_ONLY)
+    if args.serial_lanes:
+        dec.set_serial_lanes(args.serial_lanes)
     for i, p in enumerate(float(x) for x in args.ler_ps.split(",")):
         c = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
         shots = 0
+        dec.bp_time(reset=True)
+        dec.set_timing(True)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         while shots < args.ler_max_shots:
             dec.run(wl.seed, p, (i << 40) + shots, batch, c)
@@ -226,6 +232,8 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
                 break
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        dec.set_timing(False)
+        bp_ms, _ = dec.bp_time(reset=True)
         cc = c.cpu().numpy()
         f = int(cc[pk.CNT_FAIL])
         lo, hi = wilson(f, shots)
@@ -236,7 +244,11 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
                               mean_kmax=float(cc[pk.CNT_SUM_KMAX]) / shots,
                               # part Z sees no errors (K = 0 there): mean iterations of part X
                               mean_k=float(cc[pk.CNT_SUM_K]) / (L * shots),
-                              noconv=int(cc[pk.CNT_NOCONV]), seconds=round(dt, 3))), flush=True)
+                              noconv=int(cc[pk.CNT_NOCONV]), seconds=round(dt, 3), shots_per_s=shots / dt,
+                              serial_lanes=args.serial_lanes,
+                              bp_ms=round(bp_ms, 3),
+                              edge_updates_per_s_in_bp=float(cc[pk.CNT_EDGE_UPDATES]) / (bp_ms / 1e3))),
+              flush=True)
     dec.close()
 
 

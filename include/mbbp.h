@@ -216,6 +216,16 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
 mbbp_status mbbp_run_static(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
                             int64_t *counters, void *hip_stream);
 
+/* Serial schedule (MBBP_LAYERED) with normalized min-sum or sum-product: the BP
+ * kernel runs one shot per lane, `lanes` shots of one representation per
+ * wavefront, its messages in LDS.  lanes = 0 (default) picks the largest count
+ * that leaves room for two wavefronts per compute unit; 4, 8, 16, 32 or 64 asks
+ * for that count, used where it fits the LDS of one workgroup (else the default).
+ * Codes up to n = 1024 with at most 65535 edges per representation; others run
+ * the level-synchronous kernel.  Results do not depend on it.
+ * MBBP_EINVAL: lanes not 0, 4, 8, 16, 32 or 64. */
+mbbp_status mbbp_set_serial_lanes(mbbp_ctx *ctx, int32_t lanes);
+
 /* Launch configuration of the BP kernel (the autotuner's search space).
  * form: 0 = mbbp_decode / mbbp_decode_detail, 1 = mbbp_decode_batched / mbbp_run.
  * lanes_per_instance: 64 (one instance per wavefront; other values: MBBP_EUNSUPPORTED);

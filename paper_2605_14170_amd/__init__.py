@@ -268,6 +268,10 @@ class Decoder:
         """Noise model of sample(), run() and autotune(): DEPOLARIZING or X_ONLY."""
         _lib.check(_lib.lib().mbbp_set_noise(self._ctx, int(model)), "mbbp_set_noise")
 
+    def set_serial_lanes(self, lanes: int) -> None:
+        """Serial schedule: shots per wavefront (0 = chosen from the LDS size)."""
+        _lib.check(_lib.lib().mbbp_set_serial_lanes(self._ctx, int(lanes)), "mbbp_set_serial_lanes")
+
     def set_per_basis(self, enable: bool) -> None:
         """decode() as one BP launch per (part, representation): the naive form."""
         _lib.check(_lib.lib().mbbp_set_per_basis(self._ctx, 1 if enable else 0), "mbbp_set_per_basis")

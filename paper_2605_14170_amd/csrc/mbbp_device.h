@@ -54,6 +54,21 @@ struct DevPart {
     const int32_t *lev_ptr;
     const uint16_t *lev_chk;
     const uint4 *ltab;
+    // serial schedule, one lane per shot (bp_serial_kernel): per representation l
+    // and augmented row j (row order), rows stab_off[l] + j of
+    //   stab  [rows][dcs] u32: per row slot, variable v | t << 10 | (deg - 1) << 13 |
+    //         first edge of v << 16 (0xffffffff: absent slot), where edges are numbered
+    //         variable by variable (v's deg edges contiguous, ascending row order) and
+    //         t is the rank of row j among v's rows
+    //   scsrc [rows] syndrome source of the row (as csrc)
+    // htab [m][8] u16: the rows of H (0xffff beyond the row weight), for the halting test
+    const uint32_t *stab;
+    const int32_t *stab_off;   // [L + 1]
+    const int32_t *scsrc;
+    const uint16_t *htab;
+    int dcs;                   // slots per record row: 6 (every row of weight 6) or 8
+    int emax, maug;            // largest edge count / augmented row count of a representation
+    int serial_ok;             // the records fit their bit fields (edge ids < 65536)
 };
 
 // One BP launch (plain or persistent).
@@ -94,6 +109,9 @@ struct BPArgs {
     const float *walpha, *wbeta;
     float *ckpt;
     int ckpt_every, n_ck;
+    // serial kernel with one lane per shot: shots per wavefront, and the LDS rows of
+    // the messages [s_emax][S] and augmented syndrome words [s_nmw][S]
+    int serial_lanes, s_emax, s_nmw;
 };
 
 // Per-call parameters of the captured whole-path graph, written on device by the
@@ -207,6 +225,11 @@ bool bp_layout(const BPArgs &a, int &mpad);
 bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, int &stride);
 bool bp_dual_fits(int n, int mmax);  // a part of n variables and mmax + 1 positions fits it
 hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s);
+// Serial schedule with one lane per shot (rule NMS or SPA); a.serial_lanes,
+// a.s_emax, a.s_nmw and a.inst_bytes (LDS of the one wavefront of a block) set.
+hipError_t launch_bp_serial(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s);
+// Shots per wavefront the serial kernel is built for at n variables.
+bool serial_lanes_supported(int n, int S);
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();
 // BP kernel function most recently launched by the calling host thread.

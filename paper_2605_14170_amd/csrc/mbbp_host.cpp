@@ -241,6 +241,12 @@ struct HostPart {
     // check slot, the variable and its other edges (ascending check order)
     std::vector<int32_t> lev_off{0}, lev_ptr;
     std::vector<uint16_t> lev_chk, ltab;
+    // serial schedule, one lane per shot: per-row records, row-order syndrome
+    // sources, the rows of H
+    std::vector<uint32_t> stab;
+    std::vector<int32_t> stab_off{0}, scsrc;
+    std::vector<uint16_t> htab;
+    int dcs = 8, emax = 0, maug = 0, serial_ok = 1;
 };
 
 // pair_hint: launches will run two instances per wavefront where the code fits the
@@ -411,7 +417,40 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             }
         }
         P.ltab.insert(P.ltab.end(), tab.begin(), tab.end());
+        // records of the one-lane-per-shot serial kernel, rows in order 0..Ml-1; edges
+        // numbered variable by variable, a variable's edges in ascending row order
+        {
+            const int dcs = P.uniform_dc == 6 ? 6 : 8;
+            P.dcs = dcs;
+            std::vector<std::vector<int>> vck(n);  // rows of each variable, ascending
+            for (int j = 0; j < Ml; ++j)
+                for (int v : reps[l][j]) vck[v].push_back(j);
+            std::vector<int> vstart(n + 1, 0);
+            for (int v = 0; v < n; ++v) vstart[v + 1] = vstart[v] + (int)vck[v].size();
+            if (vstart[n] > 65535) P.serial_ok = 0;
+            P.emax = std::max(P.emax, vstart[n]);
+            P.maug = std::max(P.maug, Ml);
+            for (int j = 0; j < Ml; ++j) {
+                P.scsrc.push_back(srcs[l][j]);
+                for (int k = 0; k < dcs; ++k) {
+                    uint32_t w = 0xffffffffu;  // absent slot
+                    if (k < (int)reps[l][j].size()) {
+                        const int v = reps[l][j][k];
+                        const int deg = (int)vck[v].size();
+                        const int t = (int)(std::find(vck[v].begin(), vck[v].end(), j) - vck[v].begin());
+                        w = (uint32_t)v | ((uint32_t)t << 10) | ((uint32_t)(deg - 1) << 13) |
+                            ((uint32_t)vstart[v] << 16);
+                    }
+                    P.stab.push_back(w);
+                }
+            }
+            P.stab_off.push_back(P.stab_off.back() + Ml);
+        }
     }
+    P.stab.insert(P.stab.end(), 8, 0xffffffffu);  // padding: a row's record is read as 8 words
+    P.htab.assign((size_t)m * 8, 0xffff);
+    for (int j = 0; j < m; ++j)
+        for (size_t k = 0; k < H[j].size() && k < 8; ++k) P.htab[(size_t)j * 8 + k] = (uint16_t)H[j][k];
     return MBBP_OK;
 }
 
@@ -481,6 +520,7 @@ struct mbbp_ctx {
     std::unique_ptr<DevBuf> gpart;
     size_t gpart_bytes = 0;
     int cu_count = 256;
+    int lds_block = 65536;  // largest LDS of one workgroup on this device
     mbbp::BPConfig plain_cfg{16, 4, 0, 0};
     mbbp::BPConfig batched_cfg{16, 4, 8, 0};
     hipStream_t capture_stream = nullptr;
@@ -488,6 +528,7 @@ struct mbbp_ctx {
     bool use_graph = true;  // mbbp_run replays a captured graph
     hipEvent_t graph_ev[2] = {nullptr, nullptr};  // events of the captured record nodes (untimed replays)
     bool per_basis = false;  // mbbp_decode: one BP launch per (part, representation)
+    int serial_lanes = 0;    // serial schedule: shots per wavefront (0 = chosen from the LDS size)
     unsigned char *scratch_dev = nullptr;  // this device's copy of the static scratch array
     const int32_t *rep_ids = nullptr;  // device [2L]: p * L + l in order (single-pair launches)
     // BP kernel event timing
@@ -544,6 +585,14 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
         if ((st = c->put(lt, P.ltab)) != MBBP_OK) return st;
         D.ltab = reinterpret_cast<const uint4 *>(lt);
     }
+    if ((st = c->put(D.stab, P.stab)) != MBBP_OK) return st;
+    if ((st = c->put(D.stab_off, P.stab_off)) != MBBP_OK) return st;
+    if ((st = c->put(D.scsrc, P.scsrc)) != MBBP_OK) return st;
+    if ((st = c->put(D.htab, P.htab)) != MBBP_OK) return st;
+    D.dcs = P.dcs;
+    D.emax = P.emax;
+    D.maug = P.maug;
+    D.serial_ok = P.serial_ok;
     if ((st = c->put(D.comb_ptr, P.comb_ptr)) != MBBP_OK) return st;
     std::vector<int32_t> ci = P.comb_idx;
     if ((st = c->put(D.comb_idx, ci)) != MBBP_OK) return st;
@@ -632,6 +681,45 @@ mbbp_status check_stream_ptrs(const void *p, const char *what) {
     return MBBP_OK;
 }
 
+// Serial schedule with one lane per shot: shots per wavefront S and LDS bytes of its
+// wavefront (messages [E][S], augmented syndrome words, the shot's syndrome words,
+// per-shot priors).  The largest S in {64, 32, 16, 8, 4} that leaves room for two
+// wavefronts per compute unit, else the largest that fits one; false if none does
+// (the level-parallel kernel then runs the schedule).
+bool serial_lane_layout(const mbbp_ctx *c, int part0, int nparts, bool pps, mbbp::BPArgs &a) {
+    int emax = 0, maug = 0, ws = 0, n = 0;
+    for (int p = part0; p < part0 + nparts; ++p) {
+        if (!c->dp[p].serial_ok) return false;
+        emax = std::max(emax, c->dp[p].emax);
+        maug = std::max(maug, c->dp[p].maug);
+        ws = std::max(ws, c->dp[p].Ws);
+        n = std::max(n, c->dp[p].n);
+    }
+    const int nmw = (maug + 31) / 32;
+    // per shot lane: messages, decision bytes (4 a word), augmented syndrome bits,
+    // syndrome words and (per-shot priors) the priors, one word each
+    const size_t per_lane = 4u * (size_t)(emax + (n + 3) / 4 + nmw + 2 * ws + (pps ? n : 0));
+    const size_t cu_lds = 160u * 1024u;  // LDS of one gfx950 compute unit
+    int pick = 0;
+    if (c->serial_lanes > 0 && mbbp::serial_lanes_supported(n, c->serial_lanes) &&
+        (size_t)c->serial_lanes * per_lane <= (size_t)c->lds_block)
+        pick = c->serial_lanes;
+    for (int S : {64, 32, 16, 8, 4})
+        if (!pick && mbbp::serial_lanes_supported(n, S) && (size_t)S * per_lane <= (size_t)c->lds_block &&
+            2 * (size_t)S * per_lane <= cu_lds) { pick = S; break; }
+    if (!pick)
+        for (int S : {64, 32, 16, 8, 4})
+            if (mbbp::serial_lanes_supported(n, S) && (size_t)S * per_lane <= (size_t)c->lds_block) { pick = S; break; }
+    if (!pick) return false;
+    a.serial_lanes = pick;
+    a.s_emax = emax;
+    a.s_nmw = nmw;
+    a.ws_max = ws;
+    a.n_max = n;
+    a.inst_bytes = (int)((size_t)pick * per_lane + 4u * (size_t)n);  // + the shared prior vector
+    return true;
+}
+
 // Weighted-decoder training call: explicit weights, no early stop, checkpoints.
 struct WeightedCall {
     const float *alpha, *beta;
@@ -695,16 +783,30 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         a.inst_bytes = dual_bytes;
         a.dual_stride = dual_stride;
     }
+    // serial schedule: one lane per shot where its layout fits (else the level kernel)
+    const bool serial_lane = c->schedule == MBBP_LAYERED && (rule == MBBP_NMS || rule == MBBP_SPA) &&
+                             serial_lane_layout(c, part0, nparts, pps != 0, a);
+    if (serial_lane) {
+        a.dual = 0;
+        a.chunk = cfg.chunk * a.serial_lanes;  // a work item gives every lane `chunk` shots
+        a.n_chunks = (shots + a.chunk - 1) / a.chunk;
+        a.n_items = a.n_chunks * a.n_pl;
+    }
     mbbp::BPConfig run = cfg;
     if (persistent) {
         run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
         hipError_t e = mbbp::launch_reset(queue, nullptr, 0, s);
         if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("reset launch: ") + hipGetErrorString(e));
     }
-    while (run.waves_per_block > 1 && (size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
-        run.waves_per_block /= 2;
-    if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
-        return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
+    if (!serial_lane) {
+        while (run.waves_per_block > 1 && (size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
+            run.waves_per_block /= 2;
+        if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
+            return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
+    }
+    auto launch = [&](const mbbp::BPArgs &x) {
+        return serial_lane ? mbbp::launch_bp_serial(x, run, rule, s) : mbbp::launch_bp(x, run, c->schedule, rule, s);
+    };
     // timing: events around the launch(es); a captured launch (mbbp_run's graph) gets
     // event record nodes of its own after capture, given fresh events per replay
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -721,10 +823,10 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
             one.item_order = c->rep_ids + k;
             one.n_pl = 1;
             one.n_items = a.n_chunks;
-            e = mbbp::launch_bp(one, run, c->schedule, rule, s);
+            e = launch(one);
         }
     } else {
-        e = mbbp::launch_bp(a, run, c->schedule, rule, s);
+        e = launch(a);
     }
     if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("bp launch: ") + hipGetErrorString(e));
     if (c->timing && !capturing) {
@@ -914,6 +1016,12 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
         hipDeviceProp_t prop;
         MBBP_HIP(hipGetDeviceProperties(&prop, c->device));
         c->cu_count = prop.multiProcessorCount;
+        {
+            int lb = 0;
+            if (hipDeviceGetAttribute(&lb, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
+                lb > 0)
+                c->lds_block = lb;
+        }
         // device address of the static scratch array on this device (taken once per
         // device, with the device current)
         {
@@ -1456,6 +1564,15 @@ mbbp_status mbbp_prior_llr(int32_t noise, double p, float *mu) {
 mbbp_status mbbp_set_per_basis(mbbp_ctx *ctx, int32_t enable) {
     if (!ctx) return fail(MBBP_EINVAL, "null ctx");
     ctx->per_basis = enable != 0;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_set_serial_lanes(mbbp_ctx *ctx, int32_t lanes) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (lanes != 0 && lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64)
+        return fail(MBBP_EINVAL, "lanes must be 0, 4, 8, 16, 32 or 64");
+    if (ctx->serial_lanes != lanes) drop_graphs(ctx);
+    ctx->serial_lanes = lanes;
     return MBBP_OK;
 }
 
