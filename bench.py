@@ -82,6 +82,8 @@ def parse():
                          "root order, Algorithm 2) its subtree rows (tree) or as many random rows (random)")
     ap.add_argument("--ler-partitions", type=int, default=1, help="--paper-ler with tree/random: partitions")
     ap.add_argument("--serial-lanes", type=int, default=0, help="serial schedule: shots per wavefront (0 = library)")
+    ap.add_argument("--serial-kernel", choices=["auto", "slots", "lanes", "levels"], default="auto",
+                    help="serial schedule kernel: eight lanes per shot, one shot per lane, or level-synchronous")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -218,6 +220,7 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
     dec.set_noise(pk.X_ONLY)
     if args.serial_lanes:
         dec.set_serial_lanes(args.serial_lanes)
+    dec.set_serial_kernel(getattr(pk, "SERIAL_" + args.serial_kernel.upper()))
     for i, p in enumerate(float(x) for x in args.ler_ps.split(",")):
         c = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
         shots = 0
@@ -245,7 +248,7 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
                               # part Z sees no errors (K = 0 there): mean iterations of part X
                               mean_k=float(cc[pk.CNT_SUM_K]) / (L * shots),
                               noconv=int(cc[pk.CNT_NOCONV]), seconds=round(dt, 3), shots_per_s=shots / dt,
-                              serial_lanes=args.serial_lanes,
+                              serial_kernel=args.serial_kernel, serial_lanes=args.serial_lanes,
                               bp_ms=round(bp_ms, 3),
                               edge_updates_per_s_in_bp=float(cc[pk.CNT_EDGE_UPDATES]) / (bp_ms / 1e3))),
               flush=True)

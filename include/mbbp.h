@@ -216,9 +216,28 @@ mbbp_status mbbp_run(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int6
 mbbp_status mbbp_run_static(mbbp_ctx *ctx, uint64_t seed, double p, int64_t shot0, int64_t shots,
                             int64_t *counters, void *hip_stream);
 
-/* Serial schedule (MBBP_LAYERED) with normalized min-sum or sum-product: the BP
- * kernel runs one shot per lane, `lanes` shots of one representation per
- * wavefront, its messages in LDS.  lanes = 0 (default) picks the largest count
+/* Kernel of the serial schedule (MBBP_LAYERED, Section II-B: rows updated one after
+ * another from the latest messages).  Every choice gives the same results.
+ *   MBBP_SERIAL_AUTO   (default) SLOTS for normalized min-sum, LANES for
+ *                      sum-product, where their LDS layouts fit, else LEVELS;
+ *   MBBP_SERIAL_SLOTS  eight lanes per shot, lane k holding slot k of the current
+ *                      row, up to eight shots of one representation per wavefront
+ *                      (normalized min-sum; sum-product runs LANES);
+ *   MBBP_SERIAL_LANES  one shot per lane (mbbp_set_serial_lanes);
+ *   MBBP_SERIAL_LEVELS one instance per wavefront, the rows of a representation
+ *                      grouped into levels of rows sharing no variable.
+ * The weighted rule always runs the flooding schedule.  MBBP_EINVAL: another value. */
+typedef enum {
+    MBBP_SERIAL_AUTO = 0,
+    MBBP_SERIAL_SLOTS = 1,
+    MBBP_SERIAL_LANES = 2,
+    MBBP_SERIAL_LEVELS = 3
+} mbbp_serial_kernel;
+mbbp_status mbbp_set_serial_kernel(mbbp_ctx *ctx, int32_t kernel);
+
+/* Serial schedule with the one-shot-per-lane kernel (MBBP_SERIAL_LANES, or AUTO
+ * with sum-product): `lanes` shots of one representation per wavefront, its
+ * messages in LDS.  lanes = 0 (default) picks the largest count
  * that leaves room for two wavefronts per compute unit; 4, 8, 16, 32 or 64 asks
  * for that count, used where it fits the LDS of one workgroup (else the default).
  * Codes up to n = 1024 with at most 65535 edges per representation; others run

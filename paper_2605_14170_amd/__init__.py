@@ -24,6 +24,7 @@ NMS, SPA, WEIGHTED = 0, 1, 2
 MIN_WEIGHT, FWS = 0, 1
 DEPOLARIZING, X_ONLY = 0, 1  # noise models (mbbp_set_noise)
 PART_X, PART_Z = 0, 1
+SERIAL_AUTO, SERIAL_SLOTS, SERIAL_LANES, SERIAL_LEVELS = 0, 1, 2, 3  # mbbp_set_serial_kernel
 
 CNT_FAIL, CNT_FAIL_X, CNT_FAIL_Z, CNT_SUM_KMAX, CNT_SUM_K, CNT_EDGE_UPDATES, CNT_NOCONV, CNT_TIES = range(8)
 
@@ -267,6 +268,11 @@ class Decoder:
     def set_noise(self, model: int) -> None:
         """Noise model of sample(), run() and autotune(): DEPOLARIZING or X_ONLY."""
         _lib.check(_lib.lib().mbbp_set_noise(self._ctx, int(model)), "mbbp_set_noise")
+
+    def set_serial_kernel(self, kernel: int) -> None:
+        """Serial schedule kernel: SERIAL_AUTO, SERIAL_SLOTS (eight lanes per shot,
+        normalized min-sum), SERIAL_LANES (one shot per lane) or SERIAL_LEVELS."""
+        _lib.check(_lib.lib().mbbp_set_serial_kernel(self._ctx, int(kernel)), "mbbp_set_serial_kernel")
 
     def set_serial_lanes(self, lanes: int) -> None:
         """Serial schedule: shots per wavefront (0 = chosen from the LDS size)."""

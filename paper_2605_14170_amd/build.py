@@ -26,8 +26,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # messages are never NaN, no result changes).  Not for the host file, whose argument
 # checks must still see NaN.
 KERNEL_ONLY = ["-mno-amdgpu-ieee", "-fno-honor-nans"]
-SOURCES = ["mbbp_bp.hip", "mbbp_bp_dual.hip", "mbbp_bp_serial.hip", "mbbp_wbp.hip", "mbbp_kernels.hip",
-           "mbbp_host.cpp"]
+SOURCES = ["mbbp_bp.hip", "mbbp_bp_dual.hip", "mbbp_bp_serial.hip", "mbbp_bp_serial_slots.hip", "mbbp_wbp.hip",
+           "mbbp_kernels.hip", "mbbp_host.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -112,6 +112,9 @@ struct BPArgs {
     // serial kernel with one lane per shot: shots per wavefront, and the LDS rows of
     // the messages [s_emax][S] and augmented syndrome words [s_nmw][S]
     int serial_lanes, s_emax, s_nmw;
+    // serial kernel with eight lanes per shot: shots (lane groups) per wavefront, the
+    // bytes of one shot's LDS block and its decision words
+    int serial_groups, s_sb, s_ndw;
 };
 
 // Per-call parameters of the captured whole-path graph, written on device by the
@@ -230,6 +233,10 @@ hipError_t launch_bp_dual(const BPArgs &a, const BPConfig &cfg, hipStream_t s);
 hipError_t launch_bp_serial(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s);
 // Shots per wavefront the serial kernel is built for at n variables.
 bool serial_lanes_supported(int n, int S);
+// Serial schedule, normalized min-sum, eight lanes per shot (row slot k in lane k);
+// a.serial_groups, a.s_sb, a.s_ndw, a.s_emax, a.s_nmw, a.ws_max, a.n_max and
+// a.inst_bytes set.
+hipError_t launch_bp_serial_slots(const BPArgs &a, const BPConfig &cfg, hipStream_t s);
 bool bp_supported(int lpi, int passes, int dc_uniform, int rule, int schedule);
 size_t bp_lds_limit();
 // BP kernel function most recently launched by the calling host thread.

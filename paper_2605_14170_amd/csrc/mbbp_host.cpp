@@ -447,7 +447,9 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             P.stab_off.push_back(P.stab_off.back() + Ml);
         }
     }
-    P.stab.insert(P.stab.end(), 8, 0xffffffffu);  // padding: a row's record is read as 8 words
+    // padding: a row's record is read as 8 words, and the kernel with eight lanes per
+    // shot loads the records of two rows ahead
+    P.stab.insert(P.stab.end(), 16, 0xffffffffu);
     P.htab.assign((size_t)m * 8, 0xffff);
     for (int j = 0; j < m; ++j)
         for (size_t k = 0; k < H[j].size() && k < 8; ++k) P.htab[(size_t)j * 8 + k] = (uint16_t)H[j][k];
@@ -529,6 +531,7 @@ struct mbbp_ctx {
     hipEvent_t graph_ev[2] = {nullptr, nullptr};  // events of the captured record nodes (untimed replays)
     bool per_basis = false;  // mbbp_decode: one BP launch per (part, representation)
     int serial_lanes = 0;    // serial schedule: shots per wavefront (0 = chosen from the LDS size)
+    int serial_kernel = 0;   // serial schedule: MBBP_SERIAL_* (0 = automatic)
     unsigned char *scratch_dev = nullptr;  // this device's copy of the static scratch array
     const int32_t *rep_ids = nullptr;  // device [2L]: p * L + l in order (single-pair launches)
     // BP kernel event timing
@@ -720,6 +723,52 @@ bool serial_lane_layout(const mbbp_ctx *c, int part0, int nparts, bool pps, mbbp
     return true;
 }
 
+// LDS layout of the serial kernel with eight lanes per shot (normalized min-sum):
+// G shot blocks of sb bytes (messages, 8 junk words, decision words, augmented
+// syndrome words, syndrome words, per-shot priors), sb / 4 = 8 mod 32 so that the groups' blocks
+// start eight banks apart, then the shared prior vector and its decision words.  G
+// is the count (8, 4, 2, 1) that keeps the most shots resident per compute unit,
+// counting at most eight wavefronts (two per SIMD); ties go to the larger G.  Sets
+// the persistent grid to the wavefronts that fit.  False if one shot does not fit.
+bool serial_slot_layout(const mbbp_ctx *c, int part0, int nparts, bool pps, mbbp::BPArgs &a, int &waves_per_cu) {
+    int emax = 0, maug = 0, ws = 0, n = 0;
+    for (int p = part0; p < part0 + nparts; ++p) {
+        if (!c->dp[p].serial_ok || c->dp[p].max_deg > 8) return false;
+        emax = std::max(emax, c->dp[p].emax);
+        maug = std::max(maug, c->dp[p].maug);
+        ws = std::max(ws, c->dp[p].Ws);
+        n = std::max(n, c->dp[p].n);
+    }
+    if (emax > 65000) return false;  // the junk words' index must fit a record's edge field
+    const int nmw = (maug + 31) / 32, ndw = n / 32 + 1;
+    size_t sb = 4u * (size_t)(emax + 8 + ndw + nmw + 2 * ws + (pps ? n : 0));
+    sb = (sb + 15u) & ~(size_t)15u;
+    while ((sb / 4u) % 32u != 8u) sb += 16u;
+    // shared priors and their decisions; 32 bytes of slack past the last block (the
+    // exclusion sums read up to seven words past a variable's first edge)
+    const size_t tail = (pps ? 0u : 4u * (size_t)n + 4u * (size_t)ndw) + 32u;
+    const size_t cu_lds = 160u * 1024u;
+    int best = 0, best_score = 0, best_fit = 0;
+    for (int G : {8, 4, 2, 1}) {
+        const size_t bytes = (size_t)G * sb + tail;
+        if (bytes > (size_t)c->lds_block) continue;
+        const int fit = (int)std::min<size_t>(16, cu_lds / bytes);
+        const int score = G * std::min(fit, 8);
+        if (score > best_score) { best = G; best_score = score; best_fit = fit; }
+    }
+    if (!best) return false;
+    a.serial_groups = best;
+    a.s_sb = (int)sb;
+    a.s_ndw = ndw;
+    a.s_emax = emax;
+    a.s_nmw = nmw;
+    a.ws_max = ws;
+    a.n_max = n;
+    a.inst_bytes = (int)((size_t)best * sb + tail);
+    waves_per_cu = best_fit;
+    return true;
+}
+
 // Weighted-decoder training call: explicit weights, no early stop, checkpoints.
 struct WeightedCall {
     const float *alpha, *beta;
@@ -783,28 +832,38 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
         a.inst_bytes = dual_bytes;
         a.dual_stride = dual_stride;
     }
-    // serial schedule: one lane per shot where its layout fits (else the level kernel)
-    const bool serial_lane = c->schedule == MBBP_LAYERED && (rule == MBBP_NMS || rule == MBBP_SPA) &&
-                             serial_lane_layout(c, part0, nparts, pps != 0, a);
-    if (serial_lane) {
+    // serial schedule: normalized min-sum on eight lanes per shot, else one lane per
+    // shot (both rules), where their layouts fit; else the level-synchronous kernel
+    const bool layered = c->schedule == MBBP_LAYERED && !wc;
+    const int sk = c->serial_kernel;
+    int slot_waves = 0;
+    const bool serial_slots = layered && rule == MBBP_NMS && (sk == MBBP_SERIAL_AUTO || sk == MBBP_SERIAL_SLOTS) &&
+                              serial_slot_layout(c, part0, nparts, pps != 0, a, slot_waves);
+    const bool serial_lane = !serial_slots && layered && (rule == MBBP_NMS || rule == MBBP_SPA) &&
+                             sk != MBBP_SERIAL_LEVELS && serial_lane_layout(c, part0, nparts, pps != 0, a);
+    if (serial_lane || serial_slots) {
         a.dual = 0;
-        a.chunk = cfg.chunk * a.serial_lanes;  // a work item gives every lane `chunk` shots
+        // a work item gives every lane (every group) `chunk` shots
+        a.chunk = cfg.chunk * (serial_lane ? a.serial_lanes : a.serial_groups);
         a.n_chunks = (shots + a.chunk - 1) / a.chunk;
         a.n_items = a.n_chunks * a.n_pl;
     }
     mbbp::BPConfig run = cfg;
     if (persistent) {
         run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
+        // the eight-lanes-per-shot kernel: as many wavefronts as the LDS holds
+        if (serial_slots) run.blocks = c->cu_count * slot_waves;
         hipError_t e = mbbp::launch_reset(queue, nullptr, 0, s);
         if (e != hipSuccess) return fail(MBBP_EDEVICE, std::string("reset launch: ") + hipGetErrorString(e));
     }
-    if (!serial_lane) {
+    if (!serial_lane && !serial_slots) {
         while (run.waves_per_block > 1 && (size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
             run.waves_per_block /= 2;
         if ((size_t)run.waves_per_block * G * a.inst_bytes > mbbp::bp_lds_limit())
             return fail(MBBP_EUNSUPPORTED, "representation too large for LDS with this configuration");
     }
     auto launch = [&](const mbbp::BPArgs &x) {
+        if (serial_slots) return mbbp::launch_bp_serial_slots(x, run, s);
         return serial_lane ? mbbp::launch_bp_serial(x, run, rule, s) : mbbp::launch_bp(x, run, c->schedule, rule, s);
     };
     // timing: events around the launch(es); a captured launch (mbbp_run's graph) gets
@@ -1573,6 +1632,15 @@ mbbp_status mbbp_set_serial_lanes(mbbp_ctx *ctx, int32_t lanes) {
         return fail(MBBP_EINVAL, "lanes must be 0, 4, 8, 16, 32 or 64");
     if (ctx->serial_lanes != lanes) drop_graphs(ctx);
     ctx->serial_lanes = lanes;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_set_serial_kernel(mbbp_ctx *ctx, int32_t kernel) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    if (kernel < MBBP_SERIAL_AUTO || kernel > MBBP_SERIAL_LEVELS)
+        return fail(MBBP_EINVAL, "serial kernel must be MBBP_SERIAL_AUTO, _SLOTS, _LANES or _LEVELS");
+    if (ctx->serial_kernel != kernel) drop_graphs(ctx);
+    ctx->serial_kernel = kernel;
     return MBBP_OK;
 }
 

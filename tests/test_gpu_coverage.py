@@ -180,15 +180,19 @@ def test_nms_serial_large_codes_bit_exact(pk, factory, L, T, p, shots):
     mu = f32(oracle.prior_llr(p))
     prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
     for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
-        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
-        torch.cuda.synchronize()
         ref = oracle_decode_par(h, bp, rows, words(syn), np.full(code.n, mu), T, schedule=oracle.LAYERED,
                                 alpha=0.875, want_llr=True, precision="f32", chunk=8)
-        ks = kstat.cpu().numpy().view(np.uint16)
-        np.testing.assert_array_equal(words(cand), ref.cand)
-        np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
-        np.testing.assert_array_equal((ks >> 15).astype(bool), ref.conv)
-        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+        for kern in (pk.SERIAL_SLOTS, pk.SERIAL_LANES):
+            say(f"  part {part} serial kernel {kern}")
+            dec.set_serial_kernel(kern)
+            cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+            torch.cuda.synchronize()
+            ks = kstat.cpu().numpy().view(np.uint16)
+            np.testing.assert_array_equal(words(cand), ref.cand)
+            np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
+            np.testing.assert_array_equal((ks >> 15).astype(bool), ref.conv)
+            np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32),
+                                          ref.llr.astype(np.float32).view(np.uint32))
         say(f"  part {part}: mean K {ref.K.mean():.2f}")
     dec.close()
 
@@ -211,6 +215,9 @@ def test_per_shot_priors_decode_and_batched(pk, schedule):
     prz = rng.uniform(0.5, 6.0, (shots, code.n)).astype(np.float32)
     tx, tz = torch.from_numpy(prx).cuda(), torch.from_numpy(prz).cuda()
     outs = [dec.decode(sx, sz, tx, tz), dec.decode_batched(sx, sz, tx, tz)]
+    if schedule == 1:  # the serial schedule's one-shot-per-lane kernel too
+        dec.set_serial_kernel(pk.SERIAL_LANES)
+        outs += [dec.decode(sx, sz, tx, tz), dec.decode_batched(sx, sz, tx, tz)]
     torch.cuda.synchronize()
     for h, (bp, rows), syn, pr, tag in ((code.hz, bz, sx, prx, "x"), (code.hx, bx, sz, prz, "z")):
         ref = oracle_decode_par(h, bp, rows, words(syn), pr.astype(np.float64), wl.T, schedule=schedule,

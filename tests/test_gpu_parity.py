@@ -556,10 +556,15 @@ def test_launch_configs_bit_identical(pk, key, p):
     dec.close()
 
 
+SERIAL_KERNELS = ("SERIAL_SLOTS", "SERIAL_LANES", "SERIAL_LEVELS")
+
+
 @pytest.mark.parametrize("key,p,shots", [("bb72_L4_T20", 0.05, 3000), ("bb144_L16_T50", 0.06, 500)])
 def test_nms_serial_bit_exact_fp32(pk, key, p, shots):
-    """Serial schedule: the GPU's level-parallel sweep equals the oracle's row-order
-    sweep bit for bit (decisions, iterations, convergence, posterior bits)."""
+    """Serial schedule: each of the three serial kernels (eight lanes per shot, one
+    shot per lane, level-synchronous) equals the oracle's row-order sweep bit for bit
+    (decisions, iterations, convergence, posterior bits); the eight-lane kernel also
+    without posteriors (its other instantiation)."""
     wl = WORKLOADS[key]
     code = wl.code()
     dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots, schedule=pk.LAYERED)
@@ -568,15 +573,24 @@ def test_nms_serial_bit_exact_fp32(pk, key, p, shots):
     mu = f32(oracle.prior_llr(p))
     prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
     for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
-        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
-        torch.cuda.synchronize()
         ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), wl.T, schedule=oracle.LAYERED,
                             alpha=wl.alpha, want_llr=True, precision="f32")
-        ks = kstat.cpu().numpy().view(np.uint16)
-        np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
-        np.testing.assert_array_equal((ks >> 15).astype(bool), ref.conv)
+        for kern in SERIAL_KERNELS:
+            say(f"  part {part} kernel {kern}")
+            dec.set_serial_kernel(getattr(pk, kern))
+            cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+            torch.cuda.synchronize()
+            ks = kstat.cpu().numpy().view(np.uint16)
+            np.testing.assert_array_equal(ks & 0x7FFF, ref.K)
+            np.testing.assert_array_equal((ks >> 15).astype(bool), ref.conv)
+            np.testing.assert_array_equal(words(cand), ref.cand)
+            np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32),
+                                          ref.llr.astype(np.float32).view(np.uint32))
+        dec.set_serial_kernel(pk.SERIAL_SLOTS)
+        cand, kstat, _ = dec.decode_detail(part, syn, prior, want_llr=False)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(kstat.cpu().numpy().view(np.uint16) & 0x7FFF, ref.K)
         np.testing.assert_array_equal(words(cand), ref.cand)
-        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
         say(f"  part {part}: mean K {ref.K.mean():.3f}")
     dec.close()
 
@@ -594,13 +608,16 @@ def test_nms_serial_small_codes_bit_exact(pk, factory):
     mu = f32(oracle.prior_llr(p))
     prior = torch.full((code.n,), mu, dtype=torch.float32, device="cuda")
     for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
-        cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
-        torch.cuda.synchronize()
         ref = oracle.decode(h, bp, rows, words(syn), np.full(code.n, mu), T, schedule=oracle.LAYERED, alpha=0.8,
                             want_llr=True, precision="f32")
-        np.testing.assert_array_equal(words(cand), ref.cand)
-        np.testing.assert_array_equal(kstat.cpu().numpy().view(np.uint16) & 0x7FFF, ref.K)
-        np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32), ref.llr.astype(np.float32).view(np.uint32))
+        for kern in SERIAL_KERNELS:
+            dec.set_serial_kernel(getattr(pk, kern))
+            cand, kstat, llr = dec.decode_detail(part, syn, prior, want_llr=True)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(words(cand), ref.cand)
+            np.testing.assert_array_equal(kstat.cpu().numpy().view(np.uint16) & 0x7FFF, ref.K)
+            np.testing.assert_array_equal(llr.cpu().numpy().view(np.uint32),
+                                          ref.llr.astype(np.float32).view(np.uint32))
     dec.close()
 
 
