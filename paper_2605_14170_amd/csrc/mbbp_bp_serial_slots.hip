@@ -16,16 +16,21 @@
 // LDS of one wavefront: G shot blocks of SB bytes (SB / 4 = 8 mod 32, so the blocks
 // of the groups start eight banks apart), then the shared prior vector and the
 // decisions it gives at t = 0:
+//   junk      float [8]          what the lanes of absent slots read and write (word 0
+//                                 holds +FLT_MAX, the value an absent slot enters)
 //   messages  float [Emax]       edges numbered variable by variable, a variable's
 //                                 edges in ascending row order
-//   junk      float [8]          what the lanes of absent slots read and write
 //   decisions u32 [n / 32 + 1]   hard decision of v in bit v % 32 of word v / 32 (bit n
 //                                 is never set: the rows of H read it for padding)
 //   aug       u32 [NMW]          augmented syndrome bits
 //   synw      u32 [2 Ws]         the shot's syndrome words
-//   prior     float [n]          per-shot priors (prior_per_shot only)
-// Per row slot one record word (as for the one-lane-per-shot kernel) gives the
-// variable v, the rank t of the row among v's rows, v's degree and its first edge.
+//   prior     float [n + 1]      per-shot priors (prior_per_shot only), then a 0
+// Per row slot a record (two words, one lane's load) holds the byte offsets of the
+// slot's variable v (its first edge, the edge of this row (rank t among v's rows), its
+// prior and its decision word), the decision's bit, v's degree, whether t is v's last
+// rank, and the largest degree in the row (which bounds the exclusion sums of the whole
+// row).  An absent slot's lane reads a 0 prior and the junk words, so its value is
+// +FLT_MAX exactly, and writes only junk.
 // The exclusion sum mu_v + v's other messages in ascending row order is formed with
 // the slot's own message set to 0 first (adding +0 changes none of these sums: they
 // start at a canonical prior and are never -0).  At v's last row the posterior is
@@ -116,15 +121,18 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(size_t)(lds_u8 *)smem);
     const uint32_t SB = (uint32_t)a.s_sb;
-    const uint32_t msg_g = base + SB * (uint32_t)g;               // this group's shot block
-    const uint32_t dec_g = msg_g + 4u * (uint32_t)(a.s_emax + 8);  // after the messages and 8 junk words
+    const uint32_t blk_g = base + SB * (uint32_t)g;               // this group's shot block
+    const uint32_t msg_g = blk_g + 32u;                           // after the 8 junk words
+    const uint32_t dec_g = msg_g + 4u * (uint32_t)a.s_emax;
     const uint32_t aug_g = dec_g + 4u * (uint32_t)a.s_ndw;
     const uint32_t syn_g = aug_g + 4u * (uint32_t)a.s_nmw;
     const uint32_t pri_g = syn_g + 8u * (uint32_t)a.ws_max;
-    const uint32_t mu_a = base + SB * (uint32_t)a.serial_groups;  // shared priors [n]
-    const uint32_t dec0_a = mu_a + 4u * (uint32_t)a.n_max;        // their decisions
+    const uint32_t mu_a = base + SB * (uint32_t)a.serial_groups;  // shared priors [n], then a 0
+    const uint32_t dec0_a = mu_a + 4u * (uint32_t)(a.n_max + 1);  // their decisions
     const uint32_t gsh = 8u * (uint32_t)g;                         // the group's bits in a ballot
     const int nlanes = 8 * a.serial_groups;
+    // junk word 0: the value absent slots read first (nothing writes it later)
+    if (k == 0) *lds_ptr_f32(blk_g) = 3.402823466e38f;
 
     int64_t item;
     if (a.persistent) {
@@ -146,11 +154,10 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
         const int n = pt->n, m = pt->m, W = pt->W, Ws = pt->Ws, L = pt->L, l = ip.l;
         const int M = ((const c_i32 *)pt->M)[l];
         const int E = ((const c_i32 *)pt->E)[l];
-        const int dcs = pt->dcs;
         const int so = ((const c_i32 *)pt->stab_off)[l];
-        const uint32_t *recp = pt->stab + (size_t)so * dcs;  // per-lane (vector) loads
+        const uint2 *srec = pt->srec + (size_t)so * 8 + k;  // this slot's records (vector loads)
         const int32_t *csrc = pt->scsrc + so;
-        const uint4 *htab4 = reinterpret_cast<const uint4 *>(pt->htab);
+        const uint4 *sht4 = reinterpret_cast<const uint4 *>(pt->sht);
         const int32_t *comb_ptr = pt->comb_ptr;
         const int32_t *comb_idx = pt->comb_idx;
         const float *prior = pick2(a.prior, ip.part);
@@ -160,8 +167,9 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
         float *llr = LLR ? pick2(a.llr, ip.part) : nullptr;
         const int ndw = (n >> 5) + 1;
         if (!pps) {
-            // the prior vector and its decisions, staged once per item
-            for (int v = lane; v < n; v += nlanes) *lds_ptr_f32(mu_a + 4u * (uint32_t)v) = prior[v] + 0.0f;
+            // the prior vector (and the 0 after it) and its decisions, staged once per item
+            for (int v = lane; v <= n; v += nlanes)
+                *lds_ptr_f32(mu_a + 4u * (uint32_t)v) = v < n ? prior[v] + 0.0f : 0.0f;
             wave_sync();
             for (int w = lane; w < ndw; w += nlanes) {
                 uint32_t word = 0;
@@ -176,6 +184,7 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
         auto mu_of = [&](uint32_t v) -> float {
             return pps ? *lds_ptr_f32(pri_g + 4u * v) : *lds_ptr_f32(mu_a + 4u * v);
         };
+        const uint32_t mu_g = pps ? pri_g : mu_a;  // the priors this group reads
         // any lane of the group holding b (every lane of the wave calls it)
         auto group_any = [&](bool b) -> bool { return ((__ballot(b) >> gsh) & 0xffull) != 0ull; };
         // whether some row of H is unsatisfied by the group's decisions; rows k, k + 8,
@@ -186,14 +195,11 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
                 const int r = r0 + k;
                 uint32_t par = 0;
                 if (r < m) {
-                    const uint4 hw = htab4[r];
-                    const uint32_t h[4] = {hw.x, hw.y, hw.z, hw.w};
+                    const uint4 e0 = sht4[2 * r], e1 = sht4[2 * r + 1];
+                    const uint32_t e[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
                     par = *lds_ptr_u32(syn_g + 4u * (uint32_t)(r >> 5)) >> (r & 31);
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const uint32_t v = min((h[e >> 1] >> (16 * (e & 1))) & 0xffffu, (uint32_t)n);
-                        par ^= *lds_ptr_u32(dec_g + 4u * (v >> 5)) >> (v & 31u);
-                    }
+                    for (int t = 0; t < 8; ++t) par ^= *lds_ptr_u32(dec_g + (e[t] >> 8)) >> (e[t] & 31u);
                 }
                 un = group_any((par & 1u) != 0u) || un;
                 if (early && __ballot(busy && !un) == 0ull) break;
@@ -242,8 +248,8 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
                             *lds_ptr_u32(syn_g + 4u * (uint32_t)w) = (w & 1) ? (uint32_t)(sv >> 32) : (uint32_t)sv;
                         }
                         if (pps)
-                            for (int v = k; v < n; v += 8)
-                                *lds_ptr_f32(pri_g + 4u * (uint32_t)v) = prior[shot * n + v] + 0.0f;
+                            for (int v = k; v <= n; v += 8)
+                                *lds_ptr_f32(pri_g + 4u * (uint32_t)v) = v < n ? prior[shot * n + v] + 0.0f : 0.0f;
                     }
                     next += take;
                     wave_sync();
@@ -324,33 +330,29 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
 
             // ---------------- one sweep over the augmented rows in order
             const bool busy = shot >= 0;
-            // An absent slot (row weight below the record width, or lane k >= dcs) takes a
-            // record whose first edge is the junk words and whose rank (1) differs from its
-            // degree - 1 (0): its reads and writes stay in the junk words, it takes no
-            // decision, and its value enters the row as +FLT_MAX.
-            const uint32_t absent_rec = ((uint32_t)a.s_emax << 16) | (1u << 10);
-            const uint32_t *reck = recp + min(k, dcs - 1);
-            auto row_step = [&](uint32_t rw, int j, uint32_t augw) {
-                const bool present = k < dcs && rw != 0xffffffffu;
-                const uint32_t r = present ? rw : absent_rec;
-                const uint32_t v = r & 0x3ffu, rank = (r >> 10) & 7u, dm1 = (r >> 13) & 7u;
-                const uint32_t row_a = msg_g + 4u * (r >> 16);
-                const uint32_t own_a = row_a + 4u * rank;
+            auto row_step = [&](uint2 rec, int j, uint32_t augw) {
+                const uint32_t A = rec.x, B = rec.y;
+                const uint32_t own_a = blk_g + (A >> 16);
                 *lds_ptr_f32(own_a) = 0.0f;
-                const lds_f32 *row = lds_ptr_f32(row_a);
+                const lds_f32 *row = lds_ptr_f32(blk_g + (A & 0xffffu));
                 float x[D];
 #pragma unroll
                 for (int u = 0; u < D; ++u) x[u] = row[u];
-                const float muv = mu_of(v);
+                const float muv = *lds_ptr_f32(mu_g + (B & 0xfffu));
+                // every row read issued before the sum (none is moved into its masked add)
+                if constexpr (D == 6) asm volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]));
+                else asm volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]));
                 // mu_v + v's rows in ascending order, the own row reading 0; rows past v's
-                // degree add +0 (no change: the sum is never -0)
-                bool in[D];
-#pragma unroll
-                for (int u = 1; u < D; ++u) in[u] = (uint32_t)u <= dm1;
+                // degree add +0 (no change: the sum is never -0); no slot of the row has
+                // more than rdm + 1 rows (every lane's record carries rdm)
+                const int rdm = (__builtin_amdgcn_readfirstlane((int)B) >> 12) & 7;
                 float acc = muv + x[0];
 #pragma unroll
-                for (int u = 1; u < D; ++u) acc += in[u] ? x[u] : 0.0f;
-                const float q = present ? acc : 3.402823466e38f;
+                for (int u = 1; u < D; ++u) {
+                    if (u > rdm) break;
+                    acc += B >= ((uint32_t)u << 29) ? x[u] : 0.0f;
+                }
+                const float q = acc;
                 float m1, m2;
                 uint32_t sx;
                 group_min2(q, m1, m2, sx);
@@ -358,34 +360,33 @@ __global__ __launch_bounds__(64) void bp_serial_slots_kernel(BPArgs a) {
                 // other slots' magnitudes, rmax): min2 for the slot holding the minimum
                 const uint32_t sgn = (sx ^ (augw << (31 - (j & 31)))) & 0x80000000u;
                 const float mag = (fabsf(q) == m1) ? m2 : m1;
-                const uint32_t A = fbits(fminf(alpha * mag, rmax)) | sgn;
-                const float qn = bitsf((fbits(q) & 0x80000000u) ^ A);
+                const uint32_t Am = fbits(fminf(alpha * mag, rmax)) | sgn;
+                const float qn = bitsf((fbits(q) & 0x80000000u) ^ Am);
                 *lds_ptr_f32(own_a) = qn;
-                if (rank == dm1) {
+                if ((B & 0x8000u) != 0u) {
                     // posterior of v at its last row: the exclusion sum plus the new message;
                     // its bit cleared, then set if negative (atomics: the group's other lanes
                     // may change other bits of the word)
                     const float P = acc + qn;
-                    lds_u32 *dw = lds_ptr_u32(dec_g + 4u * (v >> 5));
-                    const uint32_t bit = 1u << (v & 31u);
+                    lds_u32 *dw = lds_ptr_u32(dec_g + ((B >> 16) & 0xffu));
+                    const uint32_t bit = 1u << (B >> 24);
                     __hip_atomic_fetch_and(dw, ~bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
                     __hip_atomic_fetch_or(dw, P < 0.0f ? bit : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    if (LLR && busy) llr[((size_t)shot * L + l) * n + v] = P;
+                    if (LLR && busy) llr[((size_t)shot * L + l) * n + ((B & 0xfffu) >> 2)] = P;
                 }
             };
             // two rows per trip, each record register reloaded (two rows ahead; the table is
-            // padded past its last row) right after its row is done
-            // (every trip issues both loads, so the wait before a row's record leaves the
-            // younger load in flight)
-            uint32_t r_a = reck[0], r_b = reck[dcs];
+            // padded past its last row) right after its row is done (every trip issues both
+            // loads, so the wait before a row's record leaves the younger load in flight)
+            uint2 r_a = srec[0], r_b = srec[8];
             uint32_t augw = 0;
             int j = 0;
             for (; j + 1 < M; j += 2) {
                 if ((j & 31) == 0) augw = *lds_ptr_u32(aug_g + 4u * (uint32_t)(j >> 5));
                 row_step(r_a, j, augw);
-                r_a = reck[(size_t)(j + 2) * dcs];
+                r_a = srec[(size_t)(j + 2) * 8];
                 row_step(r_b, j + 1, augw);
-                r_b = reck[(size_t)(j + 3) * dcs];
+                r_b = srec[(size_t)(j + 3) * 8];
             }
             if (j < M) {
                 if ((j & 31) == 0) augw = *lds_ptr_u32(aug_g + 4u * (uint32_t)(j >> 5));

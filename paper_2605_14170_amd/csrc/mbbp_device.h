@@ -69,6 +69,16 @@ struct DevPart {
     int dcs;                   // slots per record row: 6 (every row of weight 6) or 8
     int emax, maug;            // largest edge count / augmented row count of a representation
     int serial_ok;             // the records fit their bit fields (edge ids < 65536)
+    // serial schedule, eight lanes per shot (bp_serial_slots_kernel): per augmented
+    // row (rows stab_off[l] + j), byte offsets within a shot's LDS block (8 junk
+    // words, then the messages)
+    //   srec  [rows][8] (A, B): A = 32 + 4 first | (32 + 4 (first + t)) << 16,
+    //         B = 4 v | rdm << 12 | (t = deg - 1) << 15 | 4 (v >> 5) << 16 |
+    //         (v & 31) << 24 | (deg - 1) << 29, rdm the row's largest deg - 1; an absent
+    //         slot has A = 4 << 16 and B's v = n
+    //   sht   [m][8] u32: rows of H, (v & 31) | 4 (v >> 5) << 8 (v = n pads)
+    const uint2 *srec;
+    const uint32_t *sht;
 };
 
 // One BP launch (plain or persistent).

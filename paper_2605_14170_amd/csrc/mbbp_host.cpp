@@ -247,6 +247,9 @@ struct HostPart {
     std::vector<int32_t> stab_off{0}, scsrc;
     std::vector<uint16_t> htab;
     int dcs = 8, emax = 0, maug = 0, serial_ok = 1;
+    // serial schedule, eight lanes per shot: per-row slot records, and the halting
+    // test's entries of the rows of H
+    std::vector<uint32_t> srec, sht;
 };
 
 // pair_hint: launches will run two instances per wavefront where the code fits the
@@ -430,6 +433,33 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             if (vstart[n] > 65535) P.serial_ok = 0;
             P.emax = std::max(P.emax, vstart[n]);
             P.maug = std::max(P.maug, Ml);
+            // eight-lanes-per-shot records: per row 8 slots of 2 words, byte offsets
+            // within a shot's LDS block (8 junk words, then the messages):
+            //   A = 32 + 4 first | (32 + 4 (first + t)) << 16
+            //   B = 4 v | rdm << 12 | (t = deg - 1) << 15 | 4 (v >> 5) << 16 |
+            //       (v & 31) << 24 | (deg - 1) << 29
+            // rdm: the largest deg - 1 in the row.  An absent slot reads and writes the
+            // junk words (A = 4 << 16) and reads the prior of v = n (a 0 kept there): its
+            // sum is 0 + junk word 0 (+FLT_MAX).
+            if (32 + 4 * (vstart[n] + 8) > 65535) P.serial_ok = 0;
+            for (int j = 0; j < Ml; ++j) {
+                uint32_t rdm = 0;
+                for (int v : reps[l][j]) rdm = std::max(rdm, (uint32_t)vck[v].size() - 1u);
+                for (int k = 0; k < 8; ++k) {
+                    uint32_t A = 4u << 16, B = (uint32_t)(4 * n) | (rdm << 12);
+                    if (k < (int)reps[l][j].size()) {
+                        const int v = reps[l][j][k];
+                        const int deg = (int)vck[v].size();
+                        const int t = (int)(std::find(vck[v].begin(), vck[v].end(), j) - vck[v].begin());
+                        A = (uint32_t)(32 + 4 * vstart[v]) | ((uint32_t)(32 + 4 * (vstart[v] + t)) << 16);
+                        B = (uint32_t)(4 * v) | (rdm << 12) | ((uint32_t)(t == deg - 1) << 15) |
+                            ((uint32_t)(4 * (v >> 5)) << 16) | ((uint32_t)(v & 31) << 24) |
+                            ((uint32_t)(deg - 1) << 29);
+                    }
+                    P.srec.push_back(A);
+                    P.srec.push_back(B);
+                }
+            }
             for (int j = 0; j < Ml; ++j) {
                 P.scsrc.push_back(srcs[l][j]);
                 for (int k = 0; k < dcs; ++k) {
@@ -450,9 +480,20 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
     // padding: a row's record is read as 8 words, and the kernel with eight lanes per
     // shot loads the records of two rows ahead
     P.stab.insert(P.stab.end(), 16, 0xffffffffu);
+    // padding: the eight-lanes-per-shot kernel loads slot records two rows ahead
+    P.srec.insert(P.srec.end(), 2 * 16, 0u);
     P.htab.assign((size_t)m * 8, 0xffff);
     for (int j = 0; j < m; ++j)
         for (size_t k = 0; k < H[j].size() && k < 8; ++k) P.htab[(size_t)j * 8 + k] = (uint16_t)H[j][k];
+    // halting-test entries of the eight-lanes-per-shot kernel: per row of H 8 words
+    // (v & 31) | 4 (v >> 5) << 8 (bit and byte offset of v's decision word); padding
+    // takes v = n, whose bit is never set
+    P.sht.assign((size_t)m * 8, 0u);
+    for (int j = 0; j < m; ++j)
+        for (int k = 0; k < 8; ++k) {
+            const int v = k < (int)H[j].size() ? H[j][k] : n;
+            P.sht[(size_t)j * 8 + k] = (uint32_t)(v & 31) | ((uint32_t)(4 * (v >> 5)) << 8);
+        }
     return MBBP_OK;
 }
 
@@ -592,6 +633,12 @@ mbbp_status upload_part(mbbp_ctx *c, int pi, const std::vector<std::vector<uint6
     if ((st = c->put(D.stab_off, P.stab_off)) != MBBP_OK) return st;
     if ((st = c->put(D.scsrc, P.scsrc)) != MBBP_OK) return st;
     if ((st = c->put(D.htab, P.htab)) != MBBP_OK) return st;
+    {
+        const uint32_t *sr = nullptr;
+        if ((st = c->put(sr, P.srec)) != MBBP_OK) return st;
+        D.srec = reinterpret_cast<const uint2 *>(sr);
+    }
+    if ((st = c->put(D.sht, P.sht)) != MBBP_OK) return st;
     D.dcs = P.dcs;
     D.emax = P.emax;
     D.maug = P.maug;
@@ -724,8 +771,8 @@ bool serial_lane_layout(const mbbp_ctx *c, int part0, int nparts, bool pps, mbbp
 }
 
 // LDS layout of the serial kernel with eight lanes per shot (normalized min-sum):
-// G shot blocks of sb bytes (messages, 8 junk words, decision words, augmented
-// syndrome words, syndrome words, per-shot priors), sb / 4 = 8 mod 32 so that the groups' blocks
+// G shot blocks of sb bytes (8 junk words, messages, decision words, augmented
+// syndrome words, syndrome words, per-shot priors and a 0), sb / 4 = 8 mod 32 so that the groups' blocks
 // start eight banks apart, then the shared prior vector and its decision words.  G
 // is the count (8, 4, 2, 1) that keeps the most shots resident per compute unit,
 // counting at most eight wavefronts (two per SIMD); ties go to the larger G.  Sets
@@ -741,12 +788,12 @@ bool serial_slot_layout(const mbbp_ctx *c, int part0, int nparts, bool pps, mbbp
     }
     if (emax > 65000) return false;  // the junk words' index must fit a record's edge field
     const int nmw = (maug + 31) / 32, ndw = n / 32 + 1;
-    size_t sb = 4u * (size_t)(emax + 8 + ndw + nmw + 2 * ws + (pps ? n : 0));
+    size_t sb = 4u * (size_t)(emax + 8 + ndw + nmw + 2 * ws + (pps ? n + 1 : 0));
     sb = (sb + 15u) & ~(size_t)15u;
     while ((sb / 4u) % 32u != 8u) sb += 16u;
     // shared priors and their decisions; 32 bytes of slack past the last block (the
     // exclusion sums read up to seven words past a variable's first edge)
-    const size_t tail = (pps ? 0u : 4u * (size_t)n + 4u * (size_t)ndw) + 32u;
+    const size_t tail = (pps ? 0u : 4u * (size_t)(n + 1) + 4u * (size_t)ndw) + 32u;
     const size_t cu_lds = 160u * 1024u;
     int best = 0, best_score = 0, best_fit = 0;
     for (int G : {8, 4, 2, 1}) {
