@@ -15,7 +15,10 @@
 // since its damping reads the previous iteration's c->v message).  The variable
 // phase also writes its hard decision as a byte cell beside every edge, so a
 // check reads its row's decisions with its message loads (syndrome test).
-// Phases are wave-synchronous: no workgroup barrier is ever needed.
+// Phases are wave-synchronous, except for large codes under the flooding schedule,
+// where WPI wavefronts of a workgroup share one instance (each takes PV variable and
+// PC check passes of the instance's WPI * PV and WPI * PC) and workgroup barriers
+// separate the phases: half the per-lane tables each, so twice the wavefronts fit.
 #include <hip/hip_runtime.h>
 
 #include "mbbp_bp_rules.h"
@@ -58,18 +61,31 @@ __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 
 // SCHED 1: serial (Section II-B): posterior phase, syndrome test, then a sweep
 // over the conflict-free levels of the checks in which every check computes its
 // incoming messages from the latest check messages.
-template <int PV, int PC, int DC, int RULE, int SCHED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : (PV <= 5 ? 3 : 1))))
+// WPI: wavefronts per instance (1, or up to 8 for the flooding schedule with NMS or
+// sum-product: then one instance per workgroup of WPI wavefronts, the instance's
+// passes split between them).
+template <int PV, int PC, int DC, int RULE, int SCHED, int WPI = 1>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
+    WPI > 1 ? 4 : PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : (PV <= 5 ? 3 : 1))))
 void bp_wave_kernel(BPArgs a) {
-    using LY = Layout<PC, RULE, DC>;
+    using LY = Layout<PC * WPI, RULE, DC>;
     static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
+    static_assert(WPI == 1 || (SCHED == 0 && RULE != kRuleWeighted && WPI <= 8), "shared instances: flooding NMS / SPA");
     constexpr int S = LY::S;  // slot stride of the LDS arrays (words)
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
+    const int sub = WPI > 1 ? wib : 0;  // this wave's share of the instance's passes
     extern __shared__ __align__(16) unsigned char smem[];
     // 32-bit LDS byte addresses of this wave's instance (wave-uniform: scalar registers)
     const uint32_t ibase_addr = (uint32_t)__builtin_amdgcn_readfirstlane(
-        (int)((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)(wib * a.inst_bytes)));
+        (int)((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)(WPI > 1 ? 0 : wib * a.inst_bytes)));
+    // shared instances: the work item and two halting flags after the instance's LDS
+    lds_u32 *ctl = lds_ptr_u32((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)a.inst_bytes);
+    // the instance's phase boundary: its wavefronts' LDS writes seen by all of them
+    auto inst_sync = [&]() {
+        if constexpr (WPI > 1) __syncthreads();
+        else wave_sync();
+    };
     lds_u64 *synl = lds_ptr_u64(ibase_addr + LY::kTail);                           // syndrome words
     lds_u32 *stage = lds_ptr_u32(ibase_addr + LY::kTail + 8u * (uint32_t)a.ws_max);  // output staging
     lds_f32 *mul = lds_ptr_f32(ibase_addr + LY::kTail + 8u * (uint32_t)(a.ws_max + a.w_max));  // priors
@@ -77,14 +93,30 @@ void bp_wave_kernel(BPArgs a) {
                              4u * (uint32_t)a.n_max);  // serial: syndrome byte per check
     constexpr bool kMuLds = SCHED == 1;  // the serial sweep reads priors from LDS
 
-    int64_t item;
-    if (a.persistent) {
-        unsigned long long v = 0;
-        if (lane == 0) v = atomicAdd(a.queue, 1ull);
-        item = uniform_i64((long long)v);
-    } else {
-        item = (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
-    }
+    // next work item: from the queue (persistent) or the grid position; with shared
+    // instances wave 0 takes it and the workgroup reads it from LDS
+    auto next_item = [&](bool first) -> int64_t {
+        if (!a.persistent) {
+            if (!first) return a.n_items;
+            return WPI > 1 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+        }
+        if constexpr (WPI > 1) {
+            if (threadIdx.x == 0) {
+                const unsigned long long v = atomicAdd(a.queue, 1ull);
+                ctl[0] = (uint32_t)v;
+                ctl[1] = (uint32_t)(v >> 32);
+            }
+            __syncthreads();
+            const int64_t it = (int64_t)(((uint64_t)ctl[1] << 32) | ctl[0]);
+            __syncthreads();
+            return uniform_i64(it);
+        } else {
+            unsigned long long v = 0;
+            if (lane == 0) v = atomicAdd(a.queue, 1ull);
+            return uniform_i64((long long)v);
+        }
+    };
+    int64_t item = next_item(true);
     const float alpha = a.alpha, rmax = a.rmax;
     const int T = a.T;
     int cur_key = -1;
@@ -120,8 +152,8 @@ void bp_wave_kernel(BPArgs a) {
             const uint32_t sink = (uint32_t)Mmax * 8u;
 #pragma unroll
             for (int v = 0; v < PV; ++v) {
-                const int s = v * 64 + lane;
-                const bool valid = v < vp && s < n;
+                const int s = (sub * PV + v) * 64 + lane;
+                const bool valid = sub * PV + v < vp && s < n;
                 const uint32_t sk2 = sink | (sink << 16);
                 uint4 o = make_uint4(sk2, sk2, sk2, sk2);
                 int deg = 0;
@@ -145,14 +177,14 @@ void bp_wave_kernel(BPArgs a) {
             if (DC == 8) {
 #pragma unroll
                 for (int c = 0; c < PC; ++c) {
-                    const int j = c * 64 + lane;
+                    const int j = (sub * PC + c) * 64 + lane;
                     cwp[c] = j < Mmax ? (uint32_t)pt->cw[(size_t)l * Mmax + j] : 8u;
                 }
             }
             const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
 #pragma unroll
             for (int c = 0; c < PC; ++c) {
-                const int j = c * 64 + lane;
+                const int j = (sub * PC + c) * 64 + lane;
                 csrcp[c] = j < Mmax ? csrc[j] : kJunkRow;
             }
             clear_now = true;
@@ -168,27 +200,28 @@ void bp_wave_kernel(BPArgs a) {
             {
                 if (kClearPerShot || clear_now) {
                     constexpr int nz = (int)(LY::kTail / 8);
-                    for (int i = lane; i < nz; i += 64) lds_ptr_u64(ibase_addr)[i] = 0ull;
+                    for (int i = sub * 64 + lane; i < nz; i += 64 * WPI) lds_ptr_u64(ibase_addr)[i] = 0ull;
                     clear_now = false;
                 }
-                if (lane < Ws) synl[lane] = syn[shot * Ws + lane];
+                if (sub == 0 && lane < Ws) synl[lane] = syn[shot * Ws + lane];
                 if (a.prior_per_shot || kMuLds) {
                     const float *pr = prior + (a.prior_per_shot ? shot * n : 0);
-                    for (int i = lane; i < n; i += 64) mul[i] = pr[i] + 0.0f;
+                    for (int i = sub * 64 + lane; i < n; i += 64 * WPI) mul[i] = pr[i] + 0.0f;
                 }
+                if (WPI > 1 && threadIdx.x == 0) ctl[2] = ctl[3] = 0u;  // halting flags
             }
-            wave_sync();
+            inst_sync();
             if (a.prior_per_shot) {
 #pragma unroll
                 for (int v = 0; v < PV; ++v) {
-                    const int s = v * 64 + lane;
-                    mu[v] = (v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
+                    const int s = (sub * PV + v) * 64 + lane;
+                    mu[v] = (sub * PV + v < vp && s < n) ? mul[vinfo[v] & 0xffffu] + 0.0f : 0.0f;
                 }
             }
             uint32_t sbits = 0, rowv = 0;  // syndrome bit and "real check" flag per pass
 #pragma unroll
             for (int c = 0; c < PC; ++c) {
-                const int j = c * 64 + lane;
+                const int j = (sub * PC + c) * 64 + lane;
                 int src = csrcp[c];
                 asm volatile("" : "+v"(src));  // derive the syndrome word address per shot (not kept live)
                 if (src != kJunkRow) {
@@ -319,7 +352,7 @@ void bp_wave_kernel(BPArgs a) {
                         for (int k = 0; k < kMaxVarDegree; ++k) asm volatile("" : "+v"(ea[v][k]));
     #pragma unroll
                     for (int v = 0; v < PV; ++v) {
-                        if (v < vp && v * 64 + lane < n) {
+                        if (sub * PV + v < vp && (sub * PV + v) * 64 + lane < n) {
                             const int deg = (int)(vinfo[v] >> 16);
                             float Pv = 0.0f;
                             bool d = false;
@@ -353,7 +386,7 @@ void bp_wave_kernel(BPArgs a) {
                             Pl[v] = Pv;
                         }
                     }
-                    wave_sync();
+                    inst_sync();
                     // ---------------- check phase: syndrome test of the decisions, c->v messages.
                     // Rows beyond the representation's checks are junk rows (unused by it).
                     uint32_t unsat = 0;
@@ -370,7 +403,7 @@ void bp_wave_kernel(BPArgs a) {
                     }
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
-                        const int j = c * 64 + lane;
+                        const int j = (sub * PC + c) * 64 + lane;
                         const lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
     #pragma unroll
                         for (int k = 0; k < DC; ++k) qa[c][k] = row[k * S];
@@ -379,7 +412,7 @@ void bp_wave_kernel(BPArgs a) {
                     }
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
-                        const int j = c * 64 + lane;
+                        const int j = (sub * PC + c) * 64 + lane;
                         lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
                         float (&q)[DC] = qa[c];
                         if constexpr (DC == 8) {
@@ -406,7 +439,16 @@ void bp_wave_kernel(BPArgs a) {
                             for (int k = 0; k < DC; ++k) row[k * S] = q[k];
                         }
                     }
-                    const bool sat = __ballot(unsat != 0u) == 0ull;
+                    bool sat = __ballot(unsat != 0u) == 0ull;
+                    if constexpr (WPI > 1) {
+                        // the instance's test: flag it & 1 raised by any wave with an unsatisfied
+                        // row; the other flag (read last before the previous barrier, written
+                        // next after the coming one) cleared for iteration it + 1
+                        if (!sat && lane == 0) atomicOr((uint32_t *)(ctl + 2 + (it & 1)), 1u);
+                        __syncthreads();
+                        sat = ctl[2 + (it & 1)] == 0u;
+                        if (threadIdx.x == 0) ctl[2 + ((it + 1) & 1)] = 0u;
+                    }
                     // ---------------- halting (Section II-B)
                     if (!a.fixed_T) {
                         if (sat) { conv = true; K = it; break; }
@@ -416,7 +458,9 @@ void bp_wave_kernel(BPArgs a) {
                         if (it == T) { conv = kfix >= 0; K = conv ? kfix : T; break; }
                     }
                     ++it;
-                    wave_sync();
+                    // (shared instances: the flag barrier above already ordered the check
+                    // phase's writes before the next variable phase)
+                    if constexpr (WPI == 1) wave_sync();
                 }
             }
             // the output path recomputes what it derives from the variable ids (hoisting
@@ -430,36 +474,30 @@ void bp_wave_kernel(BPArgs a) {
             if (llr) {
 #pragma unroll
                 for (int v = 0; v < PV; ++v) {
-                    const int s = v * 64 + lane;
-                    if (v < vp && s < n) llr[((size_t)shot * L + l) * n + (vidc[v] & 0xffffu)] = Pl[v];
+                    const int s = (sub * PV + v) * 64 + lane;
+                    if (sub * PV + v < vp && s < n) llr[((size_t)shot * L + l) * n + (vidc[v] & 0xffffu)] = Pl[v];
                 }
             }
             // ---------------- output: bit-packed hard decisions via the staging words
-            if (lane < 2 * W) stage[lane] = 0u;
-            wave_sync();
+            if (sub == 0 && lane < 2 * W) stage[lane] = 0u;
+            inst_sync();
 #pragma unroll
             for (int v = 0; v < PV; ++v) {
-                const int s = v * 64 + lane;
-                if (v < vp && s < n && ((decb >> v) & 1u)) {
+                const int s = (sub * PV + v) * 64 + lane;
+                if (sub * PV + v < vp && s < n && ((decb >> v) & 1u)) {
                     const uint32_t id = vidc[v] & 0xffffu;
                     atomicOr((uint32_t *)(stage + (id >> 5)), 1u << (id & 31));
                 }
             }
-            wave_sync();
+            inst_sync();
             // representation-major: a work item's records are contiguous (whole-line writes)
             const size_t inst = a.cand_rm ? (size_t)l * a.shots + shot : (size_t)shot * L + l;
-            if (lane < W) cand[inst * W + lane] = ((const lds_u64 *)stage)[lane];
-            if (lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
-            wave_sync();
+            if (sub == 0 && lane < W) cand[inst * W + lane] = ((const lds_u64 *)stage)[lane];
+            if (sub == 0 && lane == 0) kstat[inst] = (uint16_t)(K | (conv ? 0x8000 : 0));
+            inst_sync();
         }
 
-        if (a.persistent) {
-            unsigned long long v = 0;
-            if (lane == 0) v = atomicAdd(a.queue, 1ull);
-            item = uniform_i64((long long)v);
-        } else {
-            item = a.n_items;
-        }
+        item = next_item(false);
     }
 }
 
@@ -520,14 +558,15 @@ bool bp_layout(const BPArgs &a, int &mpad) {
     return true;
 }
 
-template <int PV, int PC, int DC, int RULE, int SCHED>
+template <int PV, int PC, int DC, int RULE, int SCHED, int WPI = 1>
 static hipError_t launch_wave_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
-    const int wpb = cfg.waves_per_block;
-    const size_t lds = (size_t)wpb * a.inst_bytes;
-    const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
-    hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE, SCHED>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
-                       a);
-    set_last_bp_kernel(reinterpret_cast<const void *>(&bp_wave_kernel<PV, PC, DC, RULE, SCHED>));
+    // shared instances: one per workgroup of WPI waves, 16 bytes of control words after it
+    const int wpb = WPI > 1 ? WPI : cfg.waves_per_block;
+    const size_t lds = WPI > 1 ? (size_t)a.inst_bytes + 16u : (size_t)wpb * a.inst_bytes;
+    const int64_t blocks = a.persistent ? cfg.blocks : (WPI > 1 ? a.n_items : (a.n_items + wpb - 1) / wpb);
+    hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE, SCHED, WPI>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
+                       s, a);
+    set_last_bp_kernel(reinterpret_cast<const void *>(&bp_wave_kernel<PV, PC, DC, RULE, SCHED, WPI>));
     return hipGetLastError();
 }
 
@@ -535,6 +574,15 @@ template <int PV, int PC, int SCHED>
 static hipError_t launch_pair(const BPArgs &a, const BPConfig &cfg, int rule, hipStream_t s) {
     bool u6 = true;
     for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
+    // the largest codes under flooding NMS / sum-product: PV / 2 waves per instance,
+    // two variable and two check passes each
+    if constexpr (SCHED == 0 && PV >= 14 && PV == PC && PV % 2 == 0) {
+        constexpr int WPI = PV / 2;
+        if (rule == kRuleNMS)
+            return u6 ? launch_wave_t<2, 2, 6, 0, 0, WPI>(a, cfg, s) : launch_wave_t<2, 2, 8, 0, 0, WPI>(a, cfg, s);
+        if (rule == kRuleSPA)
+            return u6 ? launch_wave_t<2, 2, 6, 1, 0, WPI>(a, cfg, s) : launch_wave_t<2, 2, 8, 1, 0, WPI>(a, cfg, s);
+    }
     if (rule == kRuleNMS)
         return u6 ? launch_wave_t<PV, PC, 6, 0, SCHED>(a, cfg, s) : launch_wave_t<PV, PC, 8, 0, SCHED>(a, cfg, s);
     if (rule == kRuleSPA)
