@@ -193,8 +193,24 @@ def paper_ler_main(args, wl, code):
             bz = partition_bases(pk, code.hz, k, wl.perm_seed, args.ler_bases)
             bx = partition_bases(pk, code.hx, k, wl.perm_seed, args.ler_bases, count=len(bz[0]) - 1)
             cases.append((k, bx, bz))
+    rows = []
     for part_k, bx, bz in cases:
-        paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k)
+        rows += paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k)
+    if len(cases) > 1:
+        # over the partitions (the paper's Table II): mean and best (lowest) LER per p
+        per_p = {}
+        for r in rows:
+            per_p.setdefault(r["p"], []).append(r)
+        summary = {}
+        for p_, rs in sorted(per_p.items(), reverse=True):
+            lers = [r["ler"] for r in rs]
+            summary[str(p_)] = dict(partitions=len(rs), mean_ler=sum(lers) / len(lers), best_ler=min(lers),
+                                    worst_ler=max(lers), shots=sum(r["shots"] for r in rs),
+                                    failures=sum(r["failures"] for r in rs),
+                                    mean_k=sum(r["mean_k"] for r in rs) / len(rs),
+                                    mean_L=sum(r["L"] for r in rs) / len(rs))
+        print(json.dumps(dict(table="partitions", workload=wl.key, bases=args.ler_bases,
+                              partitions=len(cases), per_p=summary)), flush=True)
 
 
 def partition_bases(pk, h, k, seed, mode, count=None):
@@ -215,6 +231,7 @@ def partition_bases(pk, h, k, seed, mode, count=None):
 def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
     import torch
     L = len(bx[0]) - 1
+    out = []
     dec = pk.Decoder(code.hx, code.hz, bx, bz, 100, schedule=pk.LAYERED, alpha=0.875, select=pk.FWS,
                      max_batch=batch)
     dec.set_noise(pk.X_ONLY)
@@ -241,6 +258,8 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
         f = int(cc[pk.CNT_FAIL])
         lo, hi = wilson(f, shots)
         bases = wl.basis_mode if part_k is None else f"{args.ler_bases} partition {part_k}"
+        out.append(dict(p=p, ler=f / shots, shots=shots, failures=f, L=L,
+                        mean_k=float(cc[pk.CNT_SUM_K]) / (L * shots)))
         print(json.dumps(dict(workload=wl.key, code=wl.key.split("_")[0], noise="x_only", schedule="layered",
                               T=100, alpha=0.875, decision="FWS", L=L, bases=bases, p=p,
                               shots=shots, failures=f, ler=f / shots, ler_95=[lo, hi],
@@ -253,6 +272,7 @@ def paper_ler_points(args, pk, wl, code, bx, bz, batch, part_k):
                               edge_updates_per_s_in_bp=float(cc[pk.CNT_EDGE_UPDATES]) / (bp_ms / 1e3))),
               flush=True)
     dec.close()
+    return out
 
 
 def weighted_main(args, wl, code):
