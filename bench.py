@@ -385,11 +385,16 @@ def weighted_main(args, wl, code):
     print(json.dumps(line), flush=True)
 
 
-def algorithmic_hbm_bytes_per_shot(code):
-    """Bytes a shot must move to or from HBM when its errors are generated in the
-    kernel: both corrections, both convergence masks, both chosen representations
-    and the failure flag (about 69 B for n = 144)."""
+def algorithmic_hbm_bytes_per_shot(code, form="batched"):
+    """Bytes a shot must move to or from HBM.  Errors generated in the kernel: both
+    corrections, both convergence masks, both chosen representations and the failure
+    flag (about 69 B for n = 144).  Per-shot priors (a decode call): the two prior
+    vectors and syndromes in, corrections, masks and representations out (about
+    1.25 KB for n = 144)."""
     W = (code.n + 63) // 64
+    if form == "pps":
+        Ws = (code.hx.shape[0] + 63) // 64
+        return 2 * code.n * 4 + 2 * Ws * 8 + 2 * W * 8 + 2 * 8 + 2 * 2
     return 2 * W * 8 + 2 * 8 + 2 * 2 + 1
 
 
@@ -461,6 +466,7 @@ def main():
                 continue
             ex, ez, sx, sz = dec.sample(wl.seed, p, base, shots, stream)
             px, pz = pri[p] if form == "pps" else (unif[p], unif[p])
+            dec.set_stats(counters[i])  # iterations and edge updates of this decode call
             out = (dec.decode_batched if form == "pps" else dec.decode)(sx, sz, px, pz, stream)
             f = dec.failures(ex, ez, out["corr_x"], out["corr_z"], stream)
             counters[i, pk.CNT_FAIL] += (f != 0).sum()
@@ -482,22 +488,23 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     dec.set_timing(False)
+    dec.set_stats(None)
     bp_ms, bp_launches = dec.bp_time(reset=True)
     c = counters.cpu().numpy()
     total_shots = shots * len(ps) * args.steps
     n_per_p = shots * args.steps
-    edges = int(c[:, pk.CNT_EDGE_UPDATES].sum()) if form == "batched" else None
+    edges = int(c[:, pk.CNT_EDGE_UPDATES].sum())
     ms_per_step = dt * 1e3 / args.steps
     value = total_shots / dt
     per_p = {}
     for i, p in enumerate(ps):
         f = int(c[i, pk.CNT_FAIL])
         d = dict(fails=f, ler=f / n_per_p, ler_95=wilson(f, n_per_p))
-        if form == "batched":
-            d.update(mean_kmax=float(c[i, pk.CNT_SUM_KMAX]) / n_per_p,
-                     mean_k=float(c[i, pk.CNT_SUM_K]) / (n_per_p * 2 * wl.L),
-                     noconv_frac=float(c[i, pk.CNT_NOCONV]) / (n_per_p * 2),
-                     ties_frac=float(c[i, pk.CNT_TIES]) / (n_per_p * 2))
+        if form == "batched":  # the decode calls report no per-shot maximum
+            d.update(mean_kmax=float(c[i, pk.CNT_SUM_KMAX]) / n_per_p)
+        d.update(mean_k=float(c[i, pk.CNT_SUM_K]) / (n_per_p * 2 * wl.L),
+                 noconv_frac=float(c[i, pk.CNT_NOCONV]) / (n_per_p * 2),
+                 ties_frac=float(c[i, pk.CNT_TIES]) / (n_per_p * 2))
         per_p[str(p)] = d
     print(f"# timed {args.steps} steps in {dt:.3f} s; BP kernel {bp_ms:.1f} ms over {bp_launches} launches",
           file=sys.stderr, flush=True)
@@ -509,7 +516,7 @@ def main():
         achieved = edges_per_launch * OPS_PER_EDGE_UPDATE / bp_avg_s / 1e12
         traffic = recorded_traffic(wl.key, shots) if (args.form == "batched" and rule == pk.NMS and
                                                        schedule == pk.FLOODING) else None
-        alg_hbm = algorithmic_hbm_bytes_per_shot(code) * shots
+        alg_hbm = algorithmic_hbm_bytes_per_shot(code, form) * shots
         lds_tbps = edges_per_launch * LDS_BYTES_PER_EDGE_UPDATE / bp_avg_s / 1e12
         roofline = dict(
             bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="T lane-op/s", frac=achieved / VALU_PEAK_TOPS,
@@ -521,7 +528,10 @@ def main():
             lds=dict(algorithmic_bytes_per_edge_update=LDS_BYTES_PER_EDGE_UPDATE, achieved_TBps=lds_tbps,
                      peak_TBps=LDS_PEAK_TBPS, frac=lds_tbps / LDS_PEAK_TBPS),
             hbm=dict(algorithmic_bytes_per_launch=alg_hbm,
-                     algorithmic_bytes_per_shot=algorithmic_hbm_bytes_per_shot(code),
+                     algorithmic_bytes_per_shot=algorithmic_hbm_bytes_per_shot(code, form),
+                     # the algorithmic bytes moved at the BP kernel's rate, and that rate's share of HBM
+                     algorithmic_GBps=alg_hbm / bp_avg_s / 1e9,
+                     algorithmic_frac=alg_hbm / bp_avg_s / 1e9 / HBM_PEAK_GBPS,
                      achieved_GBps=(traffic / bp_avg_s / 1e9) if traffic else None, peak_GBps=HBM_PEAK_GBPS,
                      frac=(traffic / bp_avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None,
                      traffic_over_algorithmic=(traffic / alg_hbm) if traffic else None))

@@ -235,6 +235,14 @@ typedef enum {
 } mbbp_serial_kernel;
 mbbp_status mbbp_set_serial_kernel(mbbp_ctx *ctx, int32_t kernel);
 
+/* Statistics of the decode calls: with counters a device int64 [MBBP_NUM_COUNTERS]
+ * array, every later mbbp_decode / mbbp_decode_batched on this decoder ADDS its
+ * MBBP_CNT_SUM_K, MBBP_CNT_EDGE_UPDATES, MBBP_CNT_NOCONV and MBBP_CNT_TIES to it, on
+ * the call's stream (the others are left alone: those calls take no failure test).
+ * The caller owns the array and keeps it alive while set; NULL (the default) stops
+ * the accounting. */
+mbbp_status mbbp_set_stats(mbbp_ctx *ctx, int64_t *counters);
+
 /* Serial schedule with the one-shot-per-lane kernel (MBBP_SERIAL_LANES, or AUTO
  * with sum-product): `lanes` shots of one representation per wavefront, its
  * messages in LDS.  lanes = 0 (default) picks the largest count

@@ -269,6 +269,15 @@ class Decoder:
         """Noise model of sample(), run() and autotune(): DEPOLARIZING or X_ONLY."""
         _lib.check(_lib.lib().mbbp_set_noise(self._ctx, int(model)), "mbbp_set_noise")
 
+    def set_stats(self, counters=None) -> None:
+        """decode() / decode_batched() add SUM_K, EDGE_UPDATES, NOCONV and TIES to
+        `counters` (device int64 [NUM_COUNTERS], kept alive by the caller); None stops."""
+        if counters is not None:
+            _need(counters, "counters", (NUM_COUNTERS,), _torch().int64)
+        self._stats = counters
+        _lib.check(_lib.lib().mbbp_set_stats(self._ctx, _ptr(counters) if counters is not None else None),
+                   "mbbp_set_stats")
+
     def set_serial_kernel(self, kernel: int) -> None:
         """Serial schedule kernel: SERIAL_AUTO, SERIAL_SLOTS (eight lanes per shot,
         normalized min-sum), SERIAL_LANES (one shot per lane) or SERIAL_LEVELS."""

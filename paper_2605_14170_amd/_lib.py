@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
             "mbbp_run_static": ([P, u64, dbl, i64, i64, P, P], i32),
             "mbbp_set_serial_lanes": ([P, i32], i32),
             "mbbp_set_serial_kernel": ([P, i32], i32),
+            "mbbp_set_stats": ([P, P], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -115,4 +116,4 @@ EXPORTED = ["mbbp_params_default", "mbbp_create", "mbbp_destroy", "mbbp_decode",
             "mbbp_bp_time", "mbbp_set_config", "mbbp_get_config", "mbbp_autotune", "mbbp_set_graph",
             "mbbp_set_weights", "mbbp_wbp_ckpt_floats", "mbbp_wbp_forward", "mbbp_wbp_backward",
             "mbbp_set_noise", "mbbp_run_graph_config", "mbbp_prior_llr", "mbbp_set_per_basis", "mbbp_run_static",
-            "mbbp_set_serial_lanes", "mbbp_set_serial_kernel"]
+            "mbbp_set_serial_lanes", "mbbp_set_serial_kernel", "mbbp_set_stats"]

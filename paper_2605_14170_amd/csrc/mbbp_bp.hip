@@ -93,12 +93,14 @@ void bp_wave_kernel(BPArgs a) {
                              4u * (uint32_t)a.n_max);  // serial: syndrome byte per check
     constexpr bool kMuLds = SCHED == 1;  // the serial sweep reads priors from LDS
 
-    // next work item: from the queue (persistent) or the grid position; with shared
-    // instances wave 0 takes it and the workgroup reads it from LDS
-    auto next_item = [&](bool first) -> int64_t {
+    // next work item: from the queue (persistent), or the grid position and then a
+    // grid-sized stride (the grid is capped: its thread count must fit 32 bits); with
+    // shared instances wave 0 takes it and the workgroup reads it from LDS
+    auto next_item = [&](int64_t cur) -> int64_t {
         if (!a.persistent) {
-            if (!first) return a.n_items;
-            return WPI > 1 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * (blockDim.x >> 6) + wib;
+            const int64_t waves = WPI > 1 ? 1 : (int64_t)(blockDim.x >> 6);
+            if (cur >= 0) return cur + (int64_t)gridDim.x * waves;
+            return WPI > 1 ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * waves + wib;
         }
         if constexpr (WPI > 1) {
             if (threadIdx.x == 0) {
@@ -116,7 +118,7 @@ void bp_wave_kernel(BPArgs a) {
             return uniform_i64((long long)v);
         }
     };
-    int64_t item = next_item(true);
+    int64_t item = next_item(-1);
     const float alpha = a.alpha, rmax = a.rmax;
     const int T = a.T;
     int cur_key = -1;
@@ -497,7 +499,7 @@ void bp_wave_kernel(BPArgs a) {
             inst_sync();
         }
 
-        item = next_item(false);
+        item = next_item(item);
     }
 }
 
@@ -563,7 +565,8 @@ static hipError_t launch_wave_t(const BPArgs &a, const BPConfig &cfg, hipStream_
     // shared instances: one per workgroup of WPI waves, 16 bytes of control words after it
     const int wpb = WPI > 1 ? WPI : cfg.waves_per_block;
     const size_t lds = WPI > 1 ? (size_t)a.inst_bytes + 16u : (size_t)wpb * a.inst_bytes;
-    const int64_t blocks = a.persistent ? cfg.blocks : (WPI > 1 ? a.n_items : (a.n_items + wpb - 1) / wpb);
+    const int64_t blocks =
+        a.persistent ? cfg.blocks : plain_grid(WPI > 1 ? a.n_items : (a.n_items + wpb - 1) / wpb);
     hipLaunchKernelGGL((bp_wave_kernel<PV, PC, DC, RULE, SCHED, WPI>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
                        s, a);
     set_last_bp_kernel(reinterpret_cast<const void *>(&bp_wave_kernel<PV, PC, DC, RULE, SCHED, WPI>));

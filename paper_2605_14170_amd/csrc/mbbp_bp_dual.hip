@@ -16,7 +16,8 @@
 // other instance keeps iterating; an iteration with all c->v messages 0 computes
 // exactly what the first variable phase of a shot computes (q = P = mu).  Values are
 // those of the one-instance kernel bit for bit.  Used for normalized min-sum with
-// early stop and one prior vector; the other forms use one instance per wavefront.
+// early stop; with per-shot priors an instance's lanes load their variables' priors
+// when it takes a shot.  The other forms use one instance per wavefront.
 #include <hip/hip_runtime.h>
 
 #include "mbbp_bp_rules.h"
@@ -147,6 +148,7 @@ void bp_dual_kernel(BPArgs a) {
             decb = 0;
         }
         const uint64_t *syn = pick2(a.syn, ip.part);
+        const float *prior = pick2(a.prior, ip.part);
         uint64_t *cand = pick2(a.cand, ip.part);
         uint16_t *kstat = pick2(a.kstat, ip.part);
         float *llr = pick2(a.llr, ip.part);
@@ -201,6 +203,12 @@ void bp_dual_kernel(BPArgs a) {
                             sbits |= bit << c;
                         }
                     }
+                }
+                if (a.prior_per_shot && ((fresh >> comp) & 1u)) {
+                    const float *pr = prior + shot[comp] * n;
+#pragma unroll
+                    for (int v = 0; v < PV2; ++v)
+                        if (v * 32 + half < n) mu[v] = pr[vinfo[v] & 0xffffu] + 0.0f;
                 }
                 fresh = 0;
                 wave_sync();
@@ -340,7 +348,7 @@ void bp_dual_kernel(BPArgs a) {
             if (lane == 0) v = atomicAdd(a.queue, 1ull);
             item = uniform_i64((long long)v);
         } else {
-            item = a.n_items;
+            item += (int64_t)gridDim.x * (blockDim.x >> 6);  // grid-sized stride (capped grid)
         }
     }
 }
@@ -374,7 +382,7 @@ template <int PV2, int PC2, int DC, int MAXD, bool LLR>
 hipError_t launch_dual_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
     const int wpb = cfg.waves_per_block;
     const size_t lds = (size_t)wpb * a.inst_bytes;
-    const int64_t blocks = a.persistent ? cfg.blocks : (a.n_items + wpb - 1) / wpb;
+    const int64_t blocks = a.persistent ? cfg.blocks : plain_grid((a.n_items + wpb - 1) / wpb);
     hipLaunchKernelGGL((bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
                        a);
     set_last_bp_kernel(reinterpret_cast<const void *>(&bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>));
@@ -404,7 +412,7 @@ hipError_t launch_dual_pair(const BPArgs &a, const BPConfig &cfg, hipStream_t s)
 }  // namespace
 
 bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, int &stride) {
-    if (schedule != 0 || rule != kRuleNMS || a.fixed_T || a.prior_per_shot) return false;
+    if (schedule != 0 || rule != kRuleNMS || a.fixed_T) return false;
     if (a.chunk > kDualMaxChunk || a.chunk * a.ws_max * 8 > kDualMaxSynBytes) return false;
     DualPair d;
     if (!dual_pick(a, d)) return false;

@@ -387,7 +387,7 @@ __global__ __launch_bounds__(64) void bp_serial_kernel(BPArgs a) {
             if (lane == 0) v = atomicAdd(a.queue, 1ull);
             item = uniform_i64((long long)v);
         } else {
-            item = a.n_items;
+            item += (int64_t)gridDim.x;  // grid-sized stride (capped grid)
         }
     }
 }
@@ -403,7 +403,7 @@ hipError_t launch_serial_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int64_t blocks = a.persistent ? cfg.blocks : a.n_items;
+    const int64_t blocks = a.persistent ? cfg.blocks : plain_grid(a.n_items);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, s, a);
     set_last_bp_kernel(reinterpret_cast<const void *>(kern));
     return hipGetLastError();

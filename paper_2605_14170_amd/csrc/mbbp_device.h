@@ -194,6 +194,11 @@ struct BPConfig {
 
 hipError_t launch_bp(const BPArgs &a, const BPConfig &cfg, int schedule, int rule, hipStream_t s);
 
+// Grid of a non-persistent BP launch that wants `blocks` workgroups: capped (the
+// kernels then stride over work items by the grid size), so the dispatch's thread
+// count stays far below 2^32.
+inline int64_t plain_grid(int64_t blocks) { return blocks < 1 ? 1 : (blocks > 65536 ? 65536 : blocks); }
+
 // Adjoint of the weighted decoder's fixed-T forward map for one part: per instance
 // (l, shot), segments of ckpt_every iterations are recomputed from the stored
 // checkpoints and run backwards; per-instance dL/dalpha_t, dL/dbeta_t go to partial.

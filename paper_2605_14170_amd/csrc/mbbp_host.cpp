@@ -573,6 +573,7 @@ struct mbbp_ctx {
     bool per_basis = false;  // mbbp_decode: one BP launch per (part, representation)
     int serial_lanes = 0;    // serial schedule: shots per wavefront (0 = chosen from the LDS size)
     int serial_kernel = 0;   // serial schedule: MBBP_SERIAL_* (0 = automatic)
+    int64_t *stats = nullptr;  // device counters mbbp_decode / mbbp_decode_batched add to (or null)
     unsigned char *scratch_dev = nullptr;  // this device's copy of the static scratch array
     const int32_t *rep_ids = nullptr;  // device [2L]: p * L + l in order (single-pair launches)
     // BP kernel event timing
@@ -1252,7 +1253,7 @@ static mbbp_status decode_common(mbbp_ctx *ctx, int64_t shots, const uint64_t *s
     uint64_t *co[2] = {corr_x, corr_z};
     uint64_t *cv[2] = {conv_x, conv_z};
     int16_t *bs[2] = {basis_x, basis_z};
-    return run_select(ctx, 0, 2, shots, co, cv, bs, nullptr, nullptr, s);
+    return run_select(ctx, 0, 2, shots, co, cv, bs, ctx->stats, nullptr, s);
 }
 
 mbbp_status mbbp_decode(mbbp_ctx *ctx, int64_t shots, const uint64_t *syn_x, const uint64_t *syn_z,
@@ -1679,6 +1680,12 @@ mbbp_status mbbp_set_serial_lanes(mbbp_ctx *ctx, int32_t lanes) {
         return fail(MBBP_EINVAL, "lanes must be 0, 4, 8, 16, 32 or 64");
     if (ctx->serial_lanes != lanes) drop_graphs(ctx);
     ctx->serial_lanes = lanes;
+    return MBBP_OK;
+}
+
+mbbp_status mbbp_set_stats(mbbp_ctx *ctx, int64_t *counters) {
+    if (!ctx) return fail(MBBP_EINVAL, "null ctx");
+    ctx->stats = counters;
     return MBBP_OK;
 }
 

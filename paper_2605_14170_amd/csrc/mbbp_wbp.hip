@@ -344,6 +344,8 @@ bool wbp_backward_supported(int pv, int pc) {
 template <int PV, int PC, int DC>
 static hipError_t launch_wbp_t(const WBPBackArgs &a, int wpb, hipStream_t s) {
     const int64_t blocks = (a.n_items + wpb - 1) / wpb;
+    // one wave per item: the dispatch's thread count must fit 32 bits
+    if (blocks * 64 * wpb >= (int64_t)1 << 32) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((wbp_backward_kernel<PV, PC, DC>), dim3((unsigned)blocks), dim3(64 * wpb),
                        (size_t)wpb * a.inst_bytes, s, a);
     return hipGetLastError();

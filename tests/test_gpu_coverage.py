@@ -417,3 +417,69 @@ def test_graph_replay_timing(pk):
     say(f"  BP per launch: graph replay {res[True]:.3f} ms, direct {res[False]:.3f} ms")
     assert 0.8 <= res[True] / res[False] <= 1.25
     dec.close()
+
+
+# ------------------------------------------------------------------ plain form beyond the grid cap
+
+@pytest.mark.parametrize("case", ["paired", "shared", "serial"])
+def test_plain_grid_stride_equals_batched(pk, case):
+    """The plain form launches one workgroup per work item up to a cap of 65536 and
+    strides over the rest (the dispatch's thread count must fit 32 bits): with one
+    shot per work item and more items than the cap, its corrections, chosen
+    representations and convergence masks equal the persistent form's.  Cases: the
+    paired kernel ([[72]]), the instance shared by seven wavefronts (n = 882), the
+    serial kernel with eight lanes per shot ([[144]])."""
+    if case == "paired":
+        wl = WORKLOADS["bb72_L4_T20"]
+        code, p, shots, sched = wl.code(), 0.05, 40000, 0
+        dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
+    elif case == "shared":
+        code, p, shots, sched, L = codes.qc882(), 0.02, 12000, 0, 6
+        bx = oracle.build_bases(code.hx, "ramp", L, check_permutations(code.hx.shape[0], L, 3))
+        bz = oracle.build_bases(code.hz, "ramp", L, check_permutations(code.hz.shape[0], L, 3))
+        dec = pk.Decoder(code.hx, code.hz, bx, bz, 20, alpha=0.875, max_batch=shots)
+    else:
+        wl = WORKLOADS["bb144_L16_T50"]
+        code, p, shots, sched = wl.code(), 0.06, 20000, 1
+        dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots, schedule=pk.LAYERED)
+    dec.set_config(0, 64, 4, 1, 0)  # plain form: one shot per work item
+    say(f"plain grid stride {case}: n={code.n} shots={shots}")
+    ex, ez, sx, sz = dec.sample(21, p, 0, shots)
+    prior = torch.full((code.n,), f32(oracle.prior_llr(p)), dtype=torch.float32, device="cuda")
+    a = dec.decode(sx, sz, prior, prior)
+    b = dec.decode_batched(sx, sz, prior, prior)
+    torch.cuda.synchronize()
+    for tag in ("x", "z"):
+        np.testing.assert_array_equal(words(a[f"corr_{tag}"]), words(b[f"corr_{tag}"]))
+        np.testing.assert_array_equal(a[f"basis_{tag}"].cpu().numpy(), b[f"basis_{tag}"].cpu().numpy())
+        np.testing.assert_array_equal(words(a[f"conv_{tag}"]), words(b[f"conv_{tag}"]))
+    dec.close()
+
+
+# ------------------------------------------------------------------ decode statistics
+
+@pytest.mark.parametrize("batched", [0, 1])
+def test_decode_stats_equal_run_counters(pk, batched):
+    """mbbp_set_stats: a decode call on the sampler's syndromes with the library's
+    uniform priors adds the same SUM_K, EDGE_UPDATES, NOCONV and TIES as mbbp_run over
+    the same shots, and leaves the other counters alone."""
+    wl = WORKLOADS["bb72_L4_T20"]
+    code = wl.code()
+    shots, p = 5000, 0.05
+    dec, bx, bz = make_decoder(pk, code, wl, max_batch=shots)
+    ref = dec.run(wl.seed, p, 0, shots)
+    ex, ez, sx, sz = dec.sample(wl.seed, p, 0, shots)
+    prior = torch.full((code.n,), pk.prior_llr(p), dtype=torch.float32, device="cuda")
+    st = torch.zeros(pk.NUM_COUNTERS, dtype=torch.int64, device="cuda")
+    dec.set_stats(st)
+    (dec.decode_batched if batched else dec.decode)(sx, sz, prior, prior)
+    dec.set_stats(None)
+    (dec.decode_batched if batched else dec.decode)(sx, sz, prior, prior)  # not counted
+    torch.cuda.synchronize()
+    got, exp = st.cpu().numpy(), ref.cpu().numpy()
+    say(f"decode stats batched={batched}: {got.tolist()} vs run {exp.tolist()}")
+    for k in (pk.CNT_SUM_K, pk.CNT_EDGE_UPDATES, pk.CNT_NOCONV, pk.CNT_TIES):
+        assert got[k] == exp[k]
+    for k in (pk.CNT_FAIL, pk.CNT_FAIL_X, pk.CNT_FAIL_Z, pk.CNT_SUM_KMAX):
+        assert got[k] == 0
+    dec.close()
