@@ -193,8 +193,9 @@ enum {
 
 /* The whole path for shots [shot0, shot0 + shots): noise (mbbp_sample), the
  * batched decoder, the decision and the failure test, replayed from a HIP graph
- * captured on first use for this `shots` (direct launches while BP timing is
- * enabled, see mbbp_set_timing, or with mbbp_set_graph(ctx, 0)).  counters: device int64
+ * captured on first use for this `shots` and launch configuration (also while BP
+ * timing is enabled: the graph's own event nodes time its BP kernel, see
+ * mbbp_set_timing; direct launches with mbbp_set_graph(ctx, 0)).  counters: device int64
  * [MBBP_NUM_COUNTERS], ACCUMULATED into (the caller zeroes it).  Uniform
  * priors log((1 - q) / q) for both parts, q = 2p/3 under depolarizing noise and
  * q = p under X-only noise (mbbp_set_noise). */
