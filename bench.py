@@ -82,6 +82,8 @@ def parse():
                          "root order, Algorithm 2) its subtree rows (tree) or as many random rows (random)")
     ap.add_argument("--ler-partitions", type=int, default=1, help="--paper-ler with tree/random: partitions")
     ap.add_argument("--serial-lanes", type=int, default=0, help="serial schedule: shots per wavefront (0 = library)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the BP launch shape of the timed form with mbbp_autotune before the timed region")
     ap.add_argument("--serial-kernel", choices=["auto", "slots", "lanes", "levels"], default="auto",
                     help="serial schedule kernel: eight lanes per shot, one shot per lane, or level-synchronous")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -453,6 +455,10 @@ def main():
     if form == "per-basis":
         dec.set_per_basis(True)
     ps = list(wl.ps)
+    if args.autotune:
+        tuned = dec.autotune(1 if form in ("batched", "pps") else 0, seed=wl.seed + 77, p=ps[len(ps) // 2],
+                             shots=min(shots, 1 << 18))
+        print(f"# autotuned launch: {tuned}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     pri = {p: soft_priors(torch, code, p, shots, 1000 + i) for i, p in enumerate(ps)} if form == "pps" else None
     unif = {p: torch.full((code.n,), pk.prior_llr(p), dtype=torch.float32, device="cuda") for p in ps}

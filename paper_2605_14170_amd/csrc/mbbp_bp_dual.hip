@@ -54,8 +54,10 @@ constexpr uint64_t kLanes0 = 0x5555555555555555ull;  // lanes of instance 0
 
 // PV2 / PC2: variable / check passes of 64 lanes covering both instances; an
 // instance has 32 * PC2 check positions.  DC as in bp_wave_kernel; MAXD: largest
-// variable degree (edge words kept per variable); LLR: posteriors are written.
-template <int PV2, int PC2, int DC, int MAXD, bool LLR>
+// variable degree (edge words kept per variable); RICH: the instantiation that also
+// writes posteriors (when a.llr is set) and takes per-shot priors (when
+// a.prior_per_shot is set); the other one does neither and keeps fewer registers.
+template <int PV2, int PC2, int DC, int MAXD, bool RICH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void bp_dual_kernel(BPArgs a) {
     using LY = LayoutM<32 * PC2, kRuleNMS, DC, false, true>;  // slot pairs
@@ -96,7 +98,7 @@ void bp_dual_kernel(BPArgs a) {
     int32_t csrcp[PC2];
     uint32_t rowv = 0;   // check pass c holds a real check of this lane's instance
     uint32_t decb = 0;   // decisions of the last variable phase (as stored in the cells)
-    float Pl[LLR ? PV2 : 1];          // posteriors of the last variable phase (LLR only)
+    float Pl[RICH ? PV2 : 1];         // posteriors of the last variable phase (RICH only)
 
     while (item < a.n_items) {
         const DualItem ip = dual_item(a, item);
@@ -131,7 +133,7 @@ void bp_dual_kernel(BPArgs a) {
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
                 mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
-                if constexpr (LLR) Pl[v] = 0.0f;
+                if constexpr (RICH) Pl[v] = 0.0f;
             }
             const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
             rowv = 0;
@@ -204,7 +206,7 @@ void bp_dual_kernel(BPArgs a) {
                         }
                     }
                 }
-                if (a.prior_per_shot && ((fresh >> comp) & 1u)) {
+                if (RICH && a.prior_per_shot && ((fresh >> comp) & 1u)) {
                     const float *pr = prior + shot[comp] * n;
 #pragma unroll
                     for (int v = 0; v < PV2; ++v)
@@ -237,7 +239,7 @@ void bp_dual_kernel(BPArgs a) {
                     default: Pv = mu[v]; d = Pv < 0.0f; break;
                     }
                     decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                    if constexpr (LLR) Pl[v] = Pv;
+                    if constexpr (RICH) Pl[v] = Pv;
                 }
             }
             wave_sync();
@@ -302,7 +304,7 @@ void bp_dual_kernel(BPArgs a) {
                     const bool conv = (sat >> c) & 1u;
                     const int K = conv ? it[c] : T;
                     const size_t inst = (size_t)shot[c] * L + l;
-                    if constexpr (LLR) {
+                    if constexpr (RICH) if (llr) {
                         if (comp == c) {
 #pragma unroll
                             for (int v = 0; v < PV2; ++v)
@@ -378,14 +380,14 @@ bool dual_pick(const BPArgs &a, DualPair &out) {
     return dual_pick_passes(pv, pc, out);
 }
 
-template <int PV2, int PC2, int DC, int MAXD, bool LLR>
+template <int PV2, int PC2, int DC, int MAXD, bool RICH>
 hipError_t launch_dual_t(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
     const int wpb = cfg.waves_per_block;
     const size_t lds = (size_t)wpb * a.inst_bytes;
     const int64_t blocks = a.persistent ? cfg.blocks : plain_grid((a.n_items + wpb - 1) / wpb);
-    hipLaunchKernelGGL((bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
+    hipLaunchKernelGGL((bp_dual_kernel<PV2, PC2, DC, MAXD, RICH>), dim3((unsigned)blocks), dim3(64 * wpb), lds, s,
                        a);
-    set_last_bp_kernel(reinterpret_cast<const void *>(&bp_dual_kernel<PV2, PC2, DC, MAXD, LLR>));
+    set_last_bp_kernel(reinterpret_cast<const void *>(&bp_dual_kernel<PV2, PC2, DC, MAXD, RICH>));
     return hipGetLastError();
 }
 
@@ -397,6 +399,8 @@ hipError_t launch_dual_dc(const BPArgs &a, const BPConfig &cfg, hipStream_t s) {
         maxd = max(maxd, a.part[p].max_deg);
         llr = llr || a.llr[p] != nullptr;
     }
+    const bool rich = llr || a.prior_per_shot != 0;  // posteriors or per-shot priors
+    llr = rich;
     if (maxd <= 6)
         return llr ? launch_dual_t<PV2, PC2, DC, 6, true>(a, cfg, s) : launch_dual_t<PV2, PC2, DC, 6, false>(a, cfg, s);
     return llr ? launch_dual_t<PV2, PC2, DC, 8, true>(a, cfg, s) : launch_dual_t<PV2, PC2, DC, 8, false>(a, cfg, s);
