@@ -98,6 +98,10 @@ void bp_dual_kernel(BPArgs a) {
     int32_t csrcp[PC2];
     uint32_t rowv = 0;   // check pass c holds a real check of this lane's instance
     uint32_t decb = 0;   // decisions of the last variable phase (as stored in the cells)
+    // one positive prior mu0 on every variable of the part (checked per representation):
+    // a shot's first iteration is then known without running it (see the fresh-shot step)
+    bool uni = false;
+    float a_first = 0.0f;  // min(alpha * mu0, rmax): magnitude of every first c->v message
     float Pl[RICH ? PV2 : 1];         // posteriors of the last variable phase (RICH only)
 
     while (item < a.n_items) {
@@ -134,6 +138,15 @@ void bp_dual_kernel(BPArgs a) {
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
                 mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
                 if constexpr (RICH) Pl[v] = 0.0f;
+            }
+            if constexpr (!RICH) {
+                const float mu0 = bitsf((uint32_t)uniform_i32((int)fbits(mu[0])));  // lane 0: rank 0
+                bool same = true;
+#pragma unroll
+                for (int v = 0; v < PV2; ++v)
+                    if (v * 32 + half < n) same = same && mu[v] == mu0;
+                uni = mu0 > 0.0f && __ballot(!same) == 0ull;
+                a_first = fminf(alpha * mu0, rmax);
             }
             const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
             rowv = 0;
@@ -173,18 +186,35 @@ void bp_dual_kernel(BPArgs a) {
         wave_sync();
 
         while (shot[0] >= 0 || shot[1] >= 0) {
-            // ---------------- a fresh shot (its syndrome words already staged): c->v messages 0
-            // (an idle instance kept iterating on its last shot), derive the check bits
+            // ---------------- a fresh shot (its syndrome words already staged): derive the
+            // check bits, then the c->v messages it starts from (an idle instance kept
+            // iterating on its last shot)
             if (fresh) {
-                if ((fresh >> comp) & 1u) {
+                if (uni) {
+                    // All q = mu0 > 0 at iteration 0, so every hard decision is 0: a shot
+                    // whose syndrome is 0 has converged at K = 0 with a zero correction,
+                    // and with T = 0 every shot stops there.  Such shots are written here
+                    // without running BP.
 #pragma unroll
-                    for (int c = 0; c < PC2; ++c) {
-                        const uint32_t row = cbase_addr + 8u * (uint32_t)(c * 32 + half);
-#pragma unroll
-                        for (int u = 0; u < DC / 2; ++u) *lds_ptr_u64(row + 8u * (uint32_t)(u * S)) = 0ull;
+                    for (int c = 0; c < 2; ++c) {
+                        while ((fresh >> c) & 1u) {
+                            const lds_u64 *sy = lds_ptr_u64(sbuf_addr) + (shot[c] - ip.begin) * Ws;
+                            const uint64_t sw = lane < Ws ? sy[lane] : 0ull;
+                            const bool zero = __ballot(sw != 0ull) == 0ull;
+                            if (!zero && T > 0) break;
+                            const size_t oi = a.cand_rm ? (size_t)l * a.shots + shot[c] : (size_t)shot[c] * L + l;
+                            if (lane < W) cand[oi * W + lane] = 0ull;
+                            if (lane == 0) kstat[oi] = (uint16_t)(zero ? 0x8000 : 0);
+                            if (next < ip.end) {
+                                shot[c] = next++;
+                            } else {
+                                shot[c] = -1;
+                                fresh &= ~(1u << c);
+                            }
+                        }
                     }
+                    if (shot[0] < 0 && shot[1] < 0) break;
                 }
-                wave_sync();
                 if ((fresh >> comp) & 1u) {
                     sbits = 0;
                     const lds_u64 *sy = lds_ptr_u64(sbuf_addr) + (shot[comp] - ip.begin) * Ws;
@@ -211,6 +241,43 @@ void bp_dual_kernel(BPArgs a) {
 #pragma unroll
                     for (int v = 0; v < PV2; ++v)
                         if (v * 32 + half < n) mu[v] = pr[vinfo[v] & 0xffffu] + 0.0f;
+                }
+                if ((fresh >> comp) & 1u) {
+                    if (uni) {
+                        // iteration 0 run on paper: its check phase sees q = mu0 on every
+                        // edge, so both minima are mu0, every sign product is +, and the
+                        // message to each edge of check j is (-1)^{s_j} min(alpha mu0, rmax)
+                        // (on a row of weight 1 its one edge gets min(alpha * FLT_MAX, rmax),
+                        // the second minimum being an unused slot's FLT_MAX)
+                        const float a_one = fminf(alpha * 3.402823466e38f, rmax);
+#pragma unroll
+                        for (int c = 0; c < PC2; ++c) {
+                            const uint32_t row = cbase_addr + 8u * (uint32_t)(c * 32 + half);
+                            const uint32_t sg = ((sbits >> c) & 1u) << 31;
+                            f32x2 w;
+                            w.x = bitsf(fbits(a_first) | sg);
+                            w.y = w.x;
+                            if (DC == 8 && cwp[c] < 2u) w.x = bitsf(fbits(a_one) | sg);
+#pragma unroll
+                            for (int u = 0; u < DC / 2; ++u) {
+                                *lds_ptr_f32x2(row + 8u * (uint32_t)(u * S)) = w;
+                                if (u == 0) w.x = w.y;
+                            }
+                        }
+                    } else {
+                        // c->v messages 0: iteration 0 computes q = P = mu
+#pragma unroll
+                        for (int c = 0; c < PC2; ++c) {
+                            const uint32_t row = cbase_addr + 8u * (uint32_t)(c * 32 + half);
+#pragma unroll
+                            for (int u = 0; u < DC / 2; ++u) *lds_ptr_u64(row + 8u * (uint32_t)(u * S)) = 0ull;
+                        }
+                    }
+                }
+                if (uni) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        if ((fresh >> c) & 1u) it[c] = 1;  // iteration 0 is done
                 }
                 fresh = 0;
                 wave_sync();
