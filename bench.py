@@ -514,6 +514,19 @@ def main():
         per_p[str(p)] = d
     print(f"# timed {args.steps} steps in {dt:.3f} s; BP kernel {bp_ms:.1f} ms over {bp_launches} launches",
           file=sys.stderr, flush=True)
+    if form == "batched" and len(ps) > 1:
+        # BP time per error rate, from one more (untimed) call per p after the timed region
+        scratch = torch.zeros((1, pk.NUM_COUNTERS), dtype=torch.int64, device="cuda")
+        for i, p in enumerate(ps):
+            dec.bp_time(reset=True)
+            dec.set_timing(True)
+            dec.run(wl.seed, p, base_of(0, i), shots, scratch[0], stream)
+            torch.cuda.synchronize()
+            dec.set_timing(False)
+            ms_p, _ = dec.bp_time(reset=True)
+            per_p[str(p)]["bp_ms"] = ms_p
+        print("# BP ms per error rate: " + ", ".join(f"{p}: {per_p[str(p)]['bp_ms']:.2f}" for p in ps),
+              file=sys.stderr, flush=True)
     roofline = None
     launches_per_step = bp_launches / max(1, args.steps)
     bp_avg_s = bp_ms / 1e3 / max(1, bp_launches)

@@ -136,6 +136,11 @@ void bp_wave_kernel(BPArgs a) {
     // schedule (posteriors read c->v messages) clear them for every shot
     constexpr bool kClearPerShot = RULE == kRuleWeighted || SCHED == 1;
     bool clear_now = true;
+    // flooding min-sum with one positive prior mu0 on every variable of the part: the
+    // first iteration's outcome is known without running it (see the shot set-up)
+    constexpr bool kKnownFirst = RULE == kRuleNMS && SCHED == 0;
+    bool uni = false;
+    float a_first = 0.0f;  // min(alpha * mu0, rmax)
 
     while (item < a.n_items) {
         const ItemPos ip = decode_item(a, item);
@@ -190,6 +195,14 @@ void bp_wave_kernel(BPArgs a) {
                 csrcp[c] = j < Mmax ? csrc[j] : kJunkRow;
             }
             clear_now = true;
+            if constexpr (kKnownFirst) {
+                // every wave of an instance scans the whole prior vector, so they agree
+                const float mu0 = pr0[0] + 0.0f;
+                bool same = true;
+                for (int i = lane; i < n; i += 64) same = same && pr0[i] + 0.0f == mu0;
+                uni = !a.prior_per_shot && !a.fixed_T && mu0 > 0.0f && __ballot(!same) == 0ull;
+                a_first = fminf(alpha * mu0, rmax);
+            }
         }
         const float *prior = pick(a.prior, ip.part);
         const uint64_t *syn = pick(a.syn, ip.part);
@@ -247,6 +260,41 @@ void bp_wave_kernel(BPArgs a) {
             float Pl[PV];  // posteriors of the last variable phase (written out at the end)
 #pragma unroll
             for (int v = 0; v < PV; ++v) Pl[v] = 0.0f;
+            bool run_bp = true;
+            if (kKnownFirst && uni) {
+                // Iteration 0 with q = mu0 > 0 on every edge: every hard decision is 0,
+                // so the shot has converged at K = 0 (zero correction) iff its syndrome
+                // is 0, and with T = 0 it stops there in any case.  Otherwise both
+                // minima of every check are mu0 and every sign product is +, so the
+                // message to each edge of check j is (-1)^{s_j} min(alpha mu0, rmax) (on
+                // a row of weight 1 its one edge gets min(alpha * FLT_MAX, rmax), the
+                // second minimum being an unused slot's FLT_MAX): written here, with the
+                // decision cells 0, and BP resumes at iteration 1.
+                const uint64_t sw = lane < Ws ? synl[lane] : 0ull;
+                const bool zero = __ballot(sw != 0ull) == 0ull;
+                if (zero || T == 0) {
+                    conv = zero;
+                    K = 0;
+                    run_bp = false;
+#pragma unroll
+                    for (int v = 0; v < PV; ++v) Pl[v] = mu[v];
+                } else {
+                    const float a_one = fminf(alpha * 3.402823466e38f, rmax);
+#pragma unroll
+                    for (int c = 0; c < PC; ++c) {
+                        const int j = (sub * PC + c) * 64 + lane;
+                        lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+                        const uint32_t sg = ((sbits >> c) & 1u) << 31;
+                        const float m = bitsf(fbits(a_first) | sg);
+                        row[0] = (DC == 8 && cwp[c] < 2u) ? bitsf(fbits(a_one) | sg) : m;
+#pragma unroll
+                        for (int k = 1; k < DC; ++k) row[k * S] = m;
+                        *lds_ptr_u64(ibase_addr + LY::kDecOff + 8u * (uint32_t)j) = 0ull;
+                    }
+                    it = 1;
+                    inst_sync();
+                }
+            }
             if constexpr (SCHED == 1) {
                 const int32_t *lp = pt->lev_ptr + pt->lev_off[l];
                 const int nlev = pt->lev_off[l + 1] - pt->lev_off[l] - 1;
@@ -334,7 +382,7 @@ void bp_wave_kernel(BPArgs a) {
                     }
                     ++it;
                 }
-            } else {
+            } else if (run_bp) {
                 while (true) {
                     // ---------------- checkpoint of the c->v messages r^(it) (weighted, training)
                     if constexpr (RULE == kRuleWeighted) {
