@@ -35,7 +35,8 @@ struct ItemPos {
 __device__ __forceinline__ ItemPos decode_item(const BPArgs &a, int64_t item) {
     const int64_t rank = item / a.n_chunks;
     const int64_t ch = item - rank * a.n_chunks;
-    const int pl = a.item_order ? a.item_order[rank] : (int)rank;
+    // (a load through a generic pointer counts as divergent: keep the index uniform)
+    const int pl = __builtin_amdgcn_readfirstlane(a.item_order ? a.item_order[rank] : (int)rank);
     ItemPos p;
     p.part = a.part0 + pl / a.L;
     p.l = pl - (pl / a.L) * a.L;
@@ -73,7 +74,7 @@ void bp_wave_kernel(BPArgs a) {
     static_assert(WPI == 1 || (SCHED == 0 && RULE != kRuleWeighted && WPI <= 8), "shared instances: flooding NMS / SPA");
     constexpr int S = LY::S;  // slot stride of the LDS arrays (words)
     const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
     const int sub = WPI > 1 ? wib : 0;  // this wave's share of the instance's passes
     extern __shared__ __align__(16) unsigned char smem[];
     // 32-bit LDS byte addresses of this wave's instance (wave-uniform: scalar registers)

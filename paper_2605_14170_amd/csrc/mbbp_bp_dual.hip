@@ -36,7 +36,8 @@ struct DualItem {
 __device__ __forceinline__ DualItem dual_item(const BPArgs &a, int64_t item) {
     const int64_t rank = item / a.n_chunks;
     const int64_t ch = item - rank * a.n_chunks;
-    const int pl = a.item_order ? a.item_order[rank] : (int)rank;
+    // (a load through a generic pointer counts as divergent: keep the index uniform)
+    const int pl = __builtin_amdgcn_readfirstlane(a.item_order ? a.item_order[rank] : (int)rank);
     DualItem p;
     p.part = a.part0 + pl / a.L;
     p.l = pl - (pl / a.L) * a.L;
@@ -64,7 +65,7 @@ void bp_dual_kernel(BPArgs a) {
     static_assert(DC % 2 == 0 && LY::S % 16 == 1, "slot pairs");
     constexpr int S = LY::S;
     const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
     const int comp = lane & 1;   // instance of this lane
     const int half = lane >> 1;  // rank within the instance's pass
     extern __shared__ __align__(16) unsigned char smem[];
@@ -116,9 +117,17 @@ void bp_dual_kernel(BPArgs a) {
             const uint16_t *vid = pt->vid + (size_t)l * n;
             const uint8_t *vdg = pt->vdeg + (size_t)l * n;
             const float *pr0 = pick2(a.prior, ip.part);
+            // Absent edges of pass v (slots beyond a variable's degree) read and write a
+            // padding word of their own, Z_v: position Mpad of slot pair v / 2, word v % 2,
+            // which no check touches; the check phase zeroes it, so each variable phase
+            // reads +0 there.  Their decision cells are those of position Mmax, which no
+            // check of any representation uses.
             const uint32_t sink = (uint32_t)Mmax * 8u;
+            const uint32_t absent_dec = LY::dec(LY::edge_word(cbase_addr, sink)) << 16;
 #pragma unroll
             for (int v = 0; v < PV2; ++v) {
+                const uint32_t absent = absent_dec | (cbase_addr + 4u * ((uint32_t)(v >> 1) * 2u * (uint32_t)S +
+                                                                        2u * (uint32_t)LY::Mpad + (uint32_t)(v & 1)));
                 const int s1 = v * 32 + half;
                 const bool valid = s1 < n;
                 const uint32_t sk2 = sink | (sink << 16);
@@ -132,8 +141,10 @@ void bp_dual_kernel(BPArgs a) {
                 }
                 const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
 #pragma unroll
-                for (int k = 0; k < MAXD; ++k)
-                    ea[v][k] = LY::edge_word(cbase_addr, (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+                for (int k = 0; k < MAXD; ++k) {
+                    const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+                    ea[v][k] = e == sink ? absent : LY::edge_word(cbase_addr, e);
+                }
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
                 mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
@@ -295,14 +306,14 @@ void bp_dual_kernel(BPArgs a) {
                     bool d = false;
                     const bool prevd = (decb >> v) & 1u;
                     switch (uniform_i32(dmaxp[v])) {
-                    case 1: var_rule<1, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 2: var_rule<2, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 3: var_rule<3, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 4: if constexpr (MAXD >= 4) var_rule<4, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 5: if constexpr (MAXD >= 5) var_rule<5, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 6: if constexpr (MAXD >= 6) var_rule<6, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 7: if constexpr (MAXD >= 7) var_rule<7, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 8: if constexpr (MAXD >= 8) var_rule<8, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 1: var_rule<1, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 2: var_rule<2, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 3: var_rule<3, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 4: if constexpr (MAXD >= 4) var_rule<4, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 5: if constexpr (MAXD >= 5) var_rule<5, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 6: if constexpr (MAXD >= 6) var_rule<6, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 7: if constexpr (MAXD >= 7) var_rule<7, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                    case 8: if constexpr (MAXD >= 8) var_rule<8, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
                     default: Pv = mu[v]; d = Pv < 0.0f; break;
                     }
                     decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
@@ -346,6 +357,10 @@ void bp_dual_kernel(BPArgs a) {
                     *lds_ptr_f32x2(row + 8u * (uint32_t)(u * S)) = w;
                 }
             }
+            // the absent-edge words Z_v back to +0 for the next variable phase (lanes
+            // 0..5: slot pair half of instance comp)
+            if (half < (PV2 + 1) / 2)
+                *lds_ptr_u64(cbase_addr + 8u * ((uint32_t)half * (uint32_t)S + (uint32_t)LY::Mpad)) = 0ull;
             // ---------------- halting of each instance (Section II-B)
             const uint64_t ub = __ballot(unsat != 0u);
             uint32_t done = 0, sat = 0;

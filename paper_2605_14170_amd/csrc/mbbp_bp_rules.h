@@ -37,20 +37,39 @@ __device__ __forceinline__ uint32_t xor_all(const uint32_t (&x)[N]) {
 }
 
 // Two smallest magnitudes of a row (m1 <= m2, equal on a tie) and the XOR of all
-// sign bits.
+// sign bits.  Both are order statistics (exact, no rounding), so any comparison
+// order gives the same values: groups of three give their smallest and second
+// smallest with one min3 and one med3, and two groups (a1 <= a2, b1 <= b2) merge as
+// m1 = min(a1, b1), m2 = med3(a1, b1, min(a2, b2)): the smaller of the larger first
+// element and the two seconds.
 template <int DC>
 __device__ __forceinline__ void row_min2(const float (&q)[DC], float &m1, float &m2, uint32_t &sx) {
-    m1 = fminf(fabsf(q[0]), fabsf(q[1]));
-    m2 = fmaxf(fabsf(q[0]), fabsf(q[1]));
     uint32_t b[DC];
 #pragma unroll
     for (int k = 0; k < DC; ++k) b[k] = fbits(q[k]);
     sx = xor_all<DC>(b);
+    if constexpr (DC == 6 || DC == 8) {
+        const float a1 = fminf(fminf(fabsf(q[0]), fabsf(q[1])), fabsf(q[2]));
+        const float a2 = __builtin_amdgcn_fmed3f(fabsf(q[0]), fabsf(q[1]), fabsf(q[2]));
+        const float b1 = fminf(fminf(fabsf(q[3]), fabsf(q[4])), fabsf(q[5]));
+        const float b2 = __builtin_amdgcn_fmed3f(fabsf(q[3]), fabsf(q[4]), fabsf(q[5]));
+        m1 = fminf(a1, b1);
+        m2 = __builtin_amdgcn_fmed3f(a1, b1, fminf(a2, b2));
+        if constexpr (DC == 8) {
+            const float c1 = fminf(fabsf(q[6]), fabsf(q[7]));
+            const float c2 = fmaxf(fabsf(q[6]), fabsf(q[7]));
+            m2 = __builtin_amdgcn_fmed3f(m1, c1, fminf(m2, c2));
+            m1 = fminf(m1, c1);
+        }
+    } else {
+        m1 = fminf(fabsf(q[0]), fabsf(q[1]));
+        m2 = fmaxf(fabsf(q[0]), fabsf(q[1]));
 #pragma unroll
-    for (int k = 2; k < DC; ++k) {
-        const float a = fabsf(q[k]);
-        m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
-        m1 = fminf(m1, a);
+        for (int k = 2; k < DC; ++k) {
+            const float a = fabsf(q[k]);
+            m2 = __builtin_amdgcn_fmed3f(m1, m2, a);
+            m1 = fminf(m1, a);
+        }
     }
 }
 
@@ -72,9 +91,26 @@ struct CheckRule<kRuleNMS> {
         // keep the signed forms as values (one select plus one three-input bit
         // operation per slot), rather than letting the sign be re-split per slot
         asm volatile("" : "+v"(A1s), "+v"(A2s));
+        // all slot tests first (one asm block, so each lands in its own scalar register
+        // pair), then the selects: no select waits on the test just before it
+        uint64_t at1[DC];
+        if constexpr (DC == 6) {
+            asm volatile(
+                "v_cmp_eq_f32_e64 %0, |%6|, %12\n\t"
+                "v_cmp_eq_f32_e64 %1, |%7|, %12\n\t"
+                "v_cmp_eq_f32_e64 %2, |%8|, %12\n\t"
+                "v_cmp_eq_f32_e64 %3, |%9|, %12\n\t"
+                "v_cmp_eq_f32_e64 %4, |%10|, %12\n\t"
+                "v_cmp_eq_f32_e64 %5, |%11|, %12"
+                : "=s"(at1[0]), "=s"(at1[1]), "=s"(at1[2]), "=s"(at1[3]), "=s"(at1[4]), "=s"(at1[5])
+                : "v"(q[0]), "v"(q[1]), "v"(q[2]), "v"(q[3]), "v"(q[4]), "v"(q[5]), "v"(m1));
+        } else {
+#pragma unroll
+            for (int k = 0; k < DC; ++k) at1[k] = __ballot(fabsf(q[k]) == m1);
+        }
 #pragma unroll
         for (int k = 0; k < DC; ++k) {
-            const uint32_t mag = (fabsf(q[k]) == m1) ? A2s : A1s;
+            const uint32_t mag = __builtin_amdgcn_inverse_ballot_w64(at1[k]) ? A2s : A1s;
             q[k] = bitsf((fbits(q[k]) & 0x80000000u) ^ mag);
         }
     }
@@ -265,14 +301,16 @@ __device__ __forceinline__ float excl_sums(const float (&r)[D], float mu, float 
 // dec(ea).  prev is the decision already stored in the cells: only lanes whose
 // decision changed store it (the fewer lanes a byte store carries, the fewer of them
 // share an LDS bank), and the stores are skipped when no lane changed.
-template <int D, typename LY>
+// ZSINK: absent edges point at a word that holds +0 whenever this rule reads it (the
+// caller zeroes it between the store here and the next read), so no degree test.
+template <int D, typename LY, bool ZSINK = false>
 __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, bool prev, float &P, bool &dec) {
     constexpr uint32_t ROFF = LY::kROff;
     float r[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const float x = *lds_ptr_f32(LY::msg(ea[k]) + ROFF);
-        r[k] = k < deg ? x : 0.0f;
+        r[k] = (ZSINK || k < deg) ? x : 0.0f;
     }
     float q[D];
     const float pre = excl_sums<D>(r, mu, q);
