@@ -89,8 +89,15 @@ void bp_wave_kernel(BPArgs a) {
     };
     lds_u64 *synl = lds_ptr_u64(ibase_addr + LY::kTail);                           // syndrome words
     lds_u32 *stage = lds_ptr_u32(ibase_addr + LY::kTail + 8u * (uint32_t)a.ws_max);  // output staging
-    lds_f32 *mul = lds_ptr_f32(ibase_addr + LY::kTail + 8u * (uint32_t)(a.ws_max + a.w_max));  // priors
-    lds_u8 *sbl = lds_ptr_u8(ibase_addr + LY::kTail + 8u * (uint32_t)(a.ws_max + a.w_max) +
+    // flooding min-sum / sum-product: absent edges of pass g (slots beyond a variable's
+    // degree) read and write word g here, which the check phase zeroes, so a variable
+    // phase reads +0 there; their decision cells are those of position Mmax, which no
+    // check of any representation uses (other forms: absent edges use position Mmax)
+    constexpr bool kZSink = SCHED == 0 && RULE != kRuleWeighted;
+    const uint32_t zsk_addr = ibase_addr + LY::kTail + 8u * (uint32_t)(a.ws_max + a.w_max);
+    lds_f32 *zsk = lds_ptr_f32(zsk_addr);  // 16 words
+    lds_f32 *mul = lds_ptr_f32(zsk_addr + 64u);  // priors
+    lds_u8 *sbl = lds_ptr_u8(zsk_addr + 64u +
                              4u * (uint32_t)a.n_max);  // serial: syndrome byte per check
     constexpr bool kMuLds = SCHED == 1;  // the serial sweep reads priors from LDS
 
@@ -158,6 +165,7 @@ void bp_wave_kernel(BPArgs a) {
             const uint8_t *vdg = pt->vdeg + (size_t)l * n;
             const float *pr0 = pick(a.prior, ip.part);
             const uint32_t sink = (uint32_t)Mmax * 8u;
+            const uint32_t absent_dec = LY::dec(LY::edge_word(ibase_addr, sink)) << 16;
 #pragma unroll
             for (int v = 0; v < PV; ++v) {
                 const int s = (sub * PV + v) * 64 + lane;
@@ -172,9 +180,12 @@ void bp_wave_kernel(BPArgs a) {
                     id = vid[s];
                 }
                 const uint32_t w4[4] = {o.x, o.y, o.z, o.w};
+                const uint32_t absent = absent_dec | (zsk_addr + 4u * (uint32_t)(sub * PV + v));
 #pragma unroll
-                for (int k = 0; k < kMaxVarDegree; ++k)
-                    ea[v][k] = LY::edge_word(ibase_addr, (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+                for (int k = 0; k < kMaxVarDegree; ++k) {
+                    const uint32_t e = (w4[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+                    ea[v][k] = kZSink && e == sink ? absent : LY::edge_word(ibase_addr, e);
+                }
                 vinfo[v] = id | ((uint32_t)deg << 16);
                 dmaxp[v] = uniform_i32(wave_max_i32(deg));
                 if (!a.prior_per_shot) mu[v] = valid ? pr0[id] + 0.0f : 0.0f;
@@ -217,6 +228,7 @@ void bp_wave_kernel(BPArgs a) {
                 if (kClearPerShot || clear_now) {
                     constexpr int nz = (int)(LY::kTail / 8);
                     for (int i = sub * 64 + lane; i < nz; i += 64 * WPI) lds_ptr_u64(ibase_addr)[i] = 0ull;
+                    if (kZSink && sub == 0 && lane < 16) zsk[lane] = 0.0f;
                     clear_now = false;
                 }
                 if (sub == 0 && lane < Ws) synl[lane] = syn[shot * Ws + lane];
@@ -422,14 +434,14 @@ void bp_wave_kernel(BPArgs a) {
                                 }
                             } else {
                             switch (uniform_i32(dmaxp[v])) {
-                            case 1: var_rule<1, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 2: var_rule<2, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 3: var_rule<3, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 4: var_rule<4, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 5: var_rule<5, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 6: var_rule<6, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 7: var_rule<7, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                            case 8: var_rule<8, LY>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 1: var_rule<1, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 2: var_rule<2, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 3: var_rule<3, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 4: var_rule<4, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 5: var_rule<5, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 6: var_rule<6, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 7: var_rule<7, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
+                            case 8: var_rule<8, LY, kZSink>(ea[v], deg, mu[v], prevd, Pv, d); break;
                             default: Pv = mu[v]; d = Pv < 0.0f; break;
                             }
                             }
@@ -490,6 +502,8 @@ void bp_wave_kernel(BPArgs a) {
                             for (int k = 0; k < DC; ++k) row[k * S] = q[k];
                         }
                     }
+                    // this wave's absent-edge words back to +0 for the next variable phase
+                    if (kZSink && lane < PV) zsk[sub * PV + lane] = 0.0f;
                     bool sat = __ballot(unsat != 0u) == 0ull;
                     if constexpr (WPI > 1) {
                         // the instance's test: flag it & 1 raised by any wave with an unsatisfied

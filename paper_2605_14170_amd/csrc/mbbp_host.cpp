@@ -680,8 +680,9 @@ int lds_slots(const mbbp_ctx *c, int part0, int nparts, int mpad) {
 
 // LDS bytes of one BP instance (must match Layout in mbbp_bp_rules.h): messages
 // (slots of stride Mpad + kSlotPad words, 16-byte rounded), 8 decision bytes per row, for
-// the weighted rule the c->v messages, the syndrome words, the output staging words
-// and, for per-shot priors or the serial schedule, the shot's n priors.
+// the weighted rule the c->v messages, the syndrome words, the output staging words,
+// 16 words for absent edges and, for per-shot priors or the serial schedule, the
+// shot's n priors.
 bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, int schedule, int rule,
                  mbbp::BPArgs &a) {
     int W = 0, Ws = 0, n = 0;
@@ -703,7 +704,8 @@ bool inst_layout(const mbbp_ctx *c, int part0, int nparts, bool per_shot_prior, 
     // serial schedule: priors always staged (n floats) plus one syndrome byte per row
     const bool serial = schedule == MBBP_LAYERED;
     // the weighted rule keeps the c->v messages in a second message array
-    const int bytes = msg + dec + (rule == MBBP_WEIGHTED ? msg : 0) + Ws * 8 + W * 8 +
+    // + 16 words for the absent edges of the flooding passes
+    const int bytes = msg + dec + (rule == MBBP_WEIGHTED ? msg : 0) + Ws * 8 + W * 8 + 64 +
                       ((per_shot_prior || serial) ? n * 4 : 0) + (serial ? mpad : 0);
     a.inst_bytes = (bytes + 15) & ~15;
     return true;
