@@ -91,8 +91,9 @@ def parse():
     return ap.parse_args()
 
 
-# sources of the BP kernel; the recorded HBM traffic holds only for these as profiled
-KERNEL_SOURCES = ("mbbp_bp.hip", "mbbp_bp_dual.hip", "mbbp_bp_rules.h", "mbbp_device.h", "mbbp_wave.h")
+# sources of the headline BP kernel (the paired kernel's translation unit: its file and
+# the headers it includes); the recorded HBM traffic holds only for these as profiled
+KERNEL_SOURCES = ("mbbp_bp_dual.hip", "mbbp_bp_rules.h", "mbbp_device.h", "mbbp_wave.h")
 
 
 def recorded_traffic(workload, shots_per_launch):
