@@ -67,7 +67,7 @@ __device__ __forceinline__ T pick(const T (&v)[2], int part) { return part == 0 
 // passes split between them).
 template <int PV, int PC, int DC, int RULE, int SCHED, int WPI = 1>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
-    WPI > 1 ? 4 : PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : (PV <= 5 ? 3 : 1))))
+    WPI > 1 ? 6 : PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : (PV <= 5 ? 3 : 1))))
 void bp_wave_kernel(BPArgs a) {
     using LY = Layout<PC * WPI, RULE, DC>;
     static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
