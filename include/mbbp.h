@@ -261,7 +261,7 @@ mbbp_status mbbp_set_serial_lanes(mbbp_ctx *ctx, int32_t lanes);
  * chunk: shots per work item, decoded one after another by a wave (default 8 for
  *   form 0, 64 for form 1; the paired kernel, two instances per wavefront, serves
  *   items of at most 128 shots, larger ones run one instance per wavefront);
- * blocks: persistent grid size (form 1; 0 = 4 per compute unit).
+ * blocks: persistent grid size (form 1; 0 = 5 per compute unit).
  * Every configuration gives bit-identical outputs.  MBBP_EUNSUPPORTED if the code
  * does not fit the register tables of that lane count. */
 typedef struct {

@@ -59,9 +59,11 @@ constexpr uint64_t kLanes0 = 0x5555555555555555ull;  // lanes of instance 0
 // writes posteriors (when a.llr is set) and takes per-shot priors (when
 // a.prior_per_shot is set); the other one does neither and keeps fewer registers.
 template <int PV2, int PC2, int DC, int MAXD, bool RICH>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+// Up to three variable passes the kernel fits five wavefronts per SIMD (96 VGPRs, a few
+// spills off the loop); with five passes the spills would land in the loop, so four.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PV2 <= 3 ? 5 : 4)))
 void bp_dual_kernel(BPArgs a) {
-    using LY = LayoutM<32 * PC2, kRuleNMS, DC, false, true>;  // slot pairs
+    using LY = LayoutM<32 * PC2, kRuleNMS, DC, true, true>;  // slot pairs, DC message slots per row
     static_assert(DC % 2 == 0 && LY::S % 16 == 1, "slot pairs");
     constexpr int S = LY::S;
     const int lane = threadIdx.x & 63;
@@ -503,7 +505,10 @@ bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, in
     DualPair d;
     if (!dual_pick(a, d)) return false;
     const int mpad = 32 * d.pc;
-    const int msg = (4 * 8 * (mpad + kSlotPad) + 15) & ~15;  // LayoutM<mpad, NMS, DC, false>
+    bool u6 = true;
+    for (int p = a.part0; p < a.part0 + a.nparts; ++p) u6 = u6 && a.part[p].uniform_dc == 6;
+    const int slots = u6 ? 6 : 8;  // message slots per row: DC of the kernel launched
+    const int msg = (4 * slots * (mpad + kSlotPad) + 15) & ~15;  // LayoutM<mpad, NMS, DC, true, true>
     const int dec = (8 * mpad + 15) & ~15;
     const int bytes = msg + dec + a.w_max * 8;
     // instance regions 64 bytes off a multiple of 128: the two instances' copies of

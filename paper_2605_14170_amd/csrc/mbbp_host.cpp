@@ -900,7 +900,7 @@ mbbp_status run_bp(mbbp_ctx *c, int part0, int nparts, int64_t shots, const uint
     }
     mbbp::BPConfig run = cfg;
     if (persistent) {
-        run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 4;
+        run.blocks = cfg.blocks > 0 ? cfg.blocks : c->cu_count * 5;
         // the eight-lanes-per-shot kernel: as many wavefronts as the LDS holds
         if (serial_slots) run.blocks = c->cu_count * slot_waves;
         hipError_t e = mbbp::launch_reset(queue, nullptr, 0, s);
@@ -1165,7 +1165,7 @@ mbbp_status mbbp_create(const mbbp_sparse *H_X, const mbbp_sparse *H_Z, const mb
         if (!mbbp::bp_supported(lpi, need, c->dp[0].uniform_dc, prm.rule, schedule))
             return fail(MBBP_EUNSUPPORTED, "code too large for the register tables");
         c->plain_cfg = mbbp::BPConfig{lpi, 4, 8, 0};
-        c->batched_cfg = mbbp::BPConfig{lpi, 4, 64, c->cu_count * 4};
+        c->batched_cfg = mbbp::BPConfig{lpi, 4, 64, c->cu_count * 5};
         // workspace
         const int64_t B = prm.max_batch;
         for (int p = 0; p < 2; ++p) {
@@ -1640,7 +1640,7 @@ mbbp_status mbbp_set_config(mbbp_ctx *ctx, int32_t form, const mbbp_launch_confi
     if (cfg->chunk < 1 || cfg->chunk > (1 << 20)) return fail(MBBP_EINVAL, "chunk in [1, 2^20]");
     if (cfg->blocks < 0) return fail(MBBP_EINVAL, "blocks < 0");
     if (!config_fits(ctx, lpi)) return fail(MBBP_EUNSUPPORTED, "code too large for this lane count");
-    mbbp::BPConfig b{lpi, cfg->waves_per_block, cfg->chunk, cfg->blocks > 0 ? cfg->blocks : ctx->cu_count * 4};
+    mbbp::BPConfig b{lpi, cfg->waves_per_block, cfg->chunk, cfg->blocks > 0 ? cfg->blocks : ctx->cu_count * 5};
     if (form == 0) {
         ctx->plain_cfg = b;
     } else {
