@@ -483,3 +483,46 @@ def test_decode_stats_equal_run_counters(pk, batched):
     for k in (pk.CNT_FAIL, pk.CNT_FAIL_X, pk.CNT_FAIL_Z, pk.CNT_SUM_KMAX):
         assert got[k] == 0
     dec.close()
+
+
+# ------------------------------------------------------------------ the known first iteration
+
+@pytest.mark.parametrize("one_per_wave", [False, True])
+@pytest.mark.parametrize("T,p,prior_kind", [(0, 0.01, "uniform"), (1, 0.01, "uniform"), (2, 0.03, "uniform"),
+                                            (20, 0.005, "uniform"), (20, 0.04, "varying"),
+                                            (6, 0.04, "one negative")])
+def test_first_iteration_paths_bit_exact(pk, one_per_wave, T, p, prior_kind):
+    """Flooding min-sum with one positive prior on every variable starts a shot from
+    the first iteration's known outcome (zero syndrome: K = 0 and a zero correction
+    without BP; otherwise the first check messages written from the syndrome);
+    other prior vectors run that iteration.  Both against the FP32 oracle, bit for
+    bit, in the paired and the one-instance kernel, with T = 0, 1, 2 and at error
+    rates where many shots have a zero syndrome."""
+    wl = WORKLOADS["bb144_L16_T50"]
+    code = wl.code()
+    shots = 1500
+    dec, bx, bz = make_decoder(pk, code, wl, T=T, max_batch=shots, one_per_wave=one_per_wave)
+    ex, ez, sx, sz = dec.sample(11, p, 300, shots)
+    mu = f32(oracle.prior_llr(p))
+    rng = np.random.default_rng(7)
+    if prior_kind == "uniform":
+        pri = np.full(code.n, mu, dtype=np.float32)
+    elif prior_kind == "varying":
+        pri = (mu * rng.uniform(0.5, 1.5, code.n)).astype(np.float32)
+    else:
+        pri = np.full(code.n, mu, dtype=np.float32)
+        pri[rng.integers(code.n)] = -mu  # one variable believed flipped: decisions start non-zero
+    prior = torch.tensor(pri, dtype=torch.float32, device="cuda")
+    say(f"first-iteration paths T={T} p={p} prior={prior_kind} one_per_wave={one_per_wave}")
+    for part, h, (bp, rows), syn in ((0, code.hz, bz, sx), (1, code.hx, bx, sz)):
+        cand, kstat, _ = dec.decode_detail(part, syn, prior, want_llr=False)
+        torch.cuda.synchronize()
+        ref = oracle_decode_par(h, bp, rows, words(syn), pri.astype(np.float64), T, alpha=wl.alpha, precision="f32")
+        ks = kstat.cpu().numpy().view(np.uint16)
+        K, conv = (ks & 0x7FFF).astype(np.int32), (ks >> 15).astype(bool)
+        np.testing.assert_array_equal(K, ref.K, err_msg=f"part {part} iterations")
+        np.testing.assert_array_equal(conv, ref.conv, err_msg=f"part {part} convergence")
+        np.testing.assert_array_equal(words(cand), ref.cand, err_msg=f"part {part} hard decisions")
+        zero = int((words(syn) == 0).all(axis=1).sum())
+        say(f"  part {part}: zero syndromes {zero} of {shots}, mean K {K.mean():.3f}, converged {conv.mean():.4f}")
+    dec.close()
