@@ -9,12 +9,14 @@
 // 32 * c + (i >> 1), so 2n variables take ceil(2n / 64) passes and 2 * Mpad
 // positions 2 * Mpad / 64 passes (5 and 3 for the code above, instead of 6 and 4).
 //
-// Each instance keeps its own LDS region (messages, decisions, syndrome and staging
-// words), its own shot and iteration count.  When an instance halts (Section II-B:
-// syndrome satisfied, or T iterations) its outputs are written, its c->v messages
-// are reset to 0 and it takes the next shot of the work item at once, while the
-// other instance keeps iterating; an iteration with all c->v messages 0 computes
-// exactly what the first variable phase of a shot computes (q = P = mu).  Values are
+// Each instance keeps its own LDS region (messages, decisions), its own shot and
+// iteration count.  When an instance halts (Section II-B: syndrome satisfied, or T
+// iterations) its outputs are written (each 64-bit word of its hard decisions packed
+// by one ballot, every lane fetching the decision bits of its variable's lane), its
+// c->v messages are reset to 0 and it takes the next shot of the work item at once,
+// while the other instance keeps iterating; an iteration with all c->v messages 0
+// computes exactly what the first variable phase of a shot computes (q = P = mu), and
+// with a uniform positive prior even that iteration is written directly.  Values are
 // those of the one-instance kernel bit for bit.  Used for normalized min-sum with
 // early stop; with per-shot priors an instance's lanes load their variables' priors
 // when it takes a shot.  The other forms use one instance per wavefront.
@@ -76,10 +78,14 @@ void bp_dual_kernel(BPArgs a) {
     const uint32_t wbase_addr = (uint32_t)__builtin_amdgcn_readfirstlane(
         (int)((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)(wib * a.inst_bytes)));
     const uint32_t cbase_addr = wbase_addr + (uint32_t)(comp * istride);
-    // instance tails: output staging words; after both regions, the syndrome words of
-    // every shot of the work item (staged once per item, so no shot waits on memory)
-    const uint32_t stage_addr[2] = {wbase_addr + LY::kTail, wbase_addr + (uint32_t)istride + LY::kTail};
+    // after both regions, the syndrome words of every shot of the work item (staged
+    // once per item, so no shot waits on memory)
     const uint32_t sbuf_addr = wbase_addr + 2u * (uint32_t)istride;
+    // after the syndrome words: where each variable of the representation sits, for
+    // the bit-packed outputs (entry 64 w + t: variable 64 w + t as 2 rank | pass << 8;
+    // 31 << 8 for ids beyond n, whose pass bit is never set)
+    constexpr int kW = (32 * PV2 + 63) / 64;  // output words an instance can need
+    const uint32_t map_addr = sbuf_addr + (uint32_t)((a.chunk * a.ws_max * 8 + 15) & ~15);
 
     int64_t item;
     if (a.persistent) {
@@ -174,6 +180,15 @@ void bp_dual_kernel(BPArgs a) {
             const int nz = a.inst_bytes >> 2;
             for (int i = lane; i < nz; i += 64) lds_ptr_u32(wbase_addr)[i] = 0u;
             decb = 0;
+#pragma unroll
+            for (int w = 0; w < kW; ++w) lds_ptr_u32(map_addr)[64 * w + lane] = 31u << 8;
+            wave_sync();
+            if (comp == 0) {
+#pragma unroll
+                for (int v = 0; v < PV2; ++v)
+                    if (v * 32 + half < n)
+                        lds_ptr_u32(map_addr)[vinfo[v] & 0xffffu] = (uint32_t)(2 * half) | ((uint32_t)v << 8);
+            }
         }
         const uint64_t *syn = pick2(a.syn, ip.part);
         const float *prior = pick2(a.prior, ip.part);
@@ -374,13 +389,13 @@ void bp_dual_kernel(BPArgs a) {
             }
             if (done) {
                 wave_sync();
-                // the output path recomputes what it derives from the variable ids (hoisting
-                // those per-shot values out of the loop would keep them live, spilled, all along)
+                // the posterior output recomputes what it derives from the variable ids
+                // (hoisting those per-shot values out of the loop would keep them live)
                 uint32_t vid[PV2];
 #pragma unroll
                 for (int v = 0; v < PV2; ++v) {
                     vid[v] = vinfo[v];
-                    asm volatile("" : "+v"(vid[v]));
+                    if constexpr (RICH) asm volatile("" : "+v"(vid[v]));
                 }
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
@@ -395,22 +410,25 @@ void bp_dual_kernel(BPArgs a) {
                                 if (v * 32 + half < n) llr[inst * n + (vid[v] & 0xffffu)] = Pl[v];
                         }
                     }
-                    // bit-packed hard decisions via the instance's staging words (zero:
-                    // cleared with the region, and again after every read below)
-                    if (comp == c) {
+                    // bit-packed hard decisions: lane t of word w fetches the decision bits
+                    // of the lane holding variable 64 w + t of instance c and keeps the
+                    // bit of that variable's pass; a ballot packs the word
+                    uint64_t wb[kW];
 #pragma unroll
-                        for (int v = 0; v < PV2; ++v)
-                            if (v * 32 + half < n && ((decb >> v) & 1u)) {
-                                const uint32_t id = vid[v] & 0xffffu;
-                                atomicOr((uint32_t *)(lds_ptr_u32(stage_addr[c]) + (id >> 5)), 1u << (id & 31));
-                            }
+                    for (int w = 0; w < kW; ++w) {
+                        const uint32_t m = lds_ptr_u32(map_addr)[64 * w + lane];
+                        const uint32_t x = (uint32_t)__builtin_amdgcn_ds_bpermute(
+                            (int)(((m & 0xffu) + (uint32_t)c) << 2), (int)decb);
+                        wb[w] = __ballot((x >> (m >> 8)) & 1u);
                     }
-                    wave_sync();
                     // representation-major: a work item's records are contiguous
                     const size_t oi = a.cand_rm ? (size_t)l * a.shots + shot[c] : inst;
                     if (lane < W) {
-                        cand[oi * W + lane] = lds_ptr_u64(stage_addr[c])[lane];
-                        lds_ptr_u64(stage_addr[c])[lane] = 0ull;
+                        uint64_t word = wb[0];
+#pragma unroll
+                        for (int w = 1; w < kW; ++w)
+                            if (lane == w) word = wb[w];
+                        cand[oi * W + lane] = word;
                     }
                     if (lane == 0) kstat[oi] = (uint16_t)(K | (conv ? 0x8000 : 0));
                     it[c] = 0;
@@ -514,7 +532,8 @@ bool bp_dual_layout(const BPArgs &a, int schedule, int rule, int &inst_bytes, in
     // instance regions 64 bytes off a multiple of 128: the two instances' copies of
     // one row lie 16 banks apart, so interleaved lanes never share a bank
     stride = ((bytes + 127) & ~127) + 64;
-    inst_bytes = 2 * stride + ((a.chunk * a.ws_max * 8 + 15) & ~15);
+    // + the variable map of the output path: 64 words per output word of an instance
+    inst_bytes = 2 * stride + ((a.chunk * a.ws_max * 8 + 15) & ~15) + 4 * 64 * ((32 * d.pv + 63) / 64);
     return true;
 }
 
