@@ -69,10 +69,14 @@ template <int PV, int PC, int DC, int RULE, int SCHED, int WPI = 1>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(
     WPI > 1 ? 6 : PV <= 3 ? (RULE == kRuleWeighted ? 3 : 4) : (PV <= 5 ? 3 : 1))))
 void bp_wave_kernel(BPArgs a) {
-    using LY = Layout<PC * WPI, RULE, DC>;
+    // flooding min-sum and sum-product keep messages in slot pairs (edge (p, k) at word
+    // (k >> 1) * 2S + 2p + (k & 1)): a check row moves two slots per 8-byte access
+    constexpr bool kPairs = SCHED == 0 && RULE != kRuleWeighted;
+    using LY = LayoutM<64 * PC * WPI, RULE, DC, (PC * WPI >= 9), kPairs>;
     static_assert(RULE != kRuleWeighted || SCHED == 0, "the weighted rule is defined for flooding");
     static_assert(WPI == 1 || (SCHED == 0 && RULE != kRuleWeighted && WPI <= 8), "shared instances: flooding NMS / SPA");
     constexpr int S = LY::S;  // slot stride of the LDS arrays (words)
+    static_assert(!kPairs || (DC % 2 == 0 && S % 16 == 1), "slot pairs");
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
     const int sub = WPI > 1 ? wib : 0;  // this wave's share of the instance's passes
@@ -80,6 +84,36 @@ void bp_wave_kernel(BPArgs a) {
     // 32-bit LDS byte addresses of this wave's instance (wave-uniform: scalar registers)
     const uint32_t ibase_addr = (uint32_t)__builtin_amdgcn_readfirstlane(
         (int)((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)(WPI > 1 ? 0 : wib * a.inst_bytes)));
+    // the DC message slots of check position j (flooding: from slot pairs)
+    auto row_load = [&](int j, float (&q)[DC]) {
+        if constexpr (kPairs) {
+#pragma unroll
+            for (int u = 0; u < DC / 2; ++u) {
+                const f32x2 w = *lds_ptr_f32x2(ibase_addr + 8u * ((uint32_t)(u * S) + (uint32_t)j));
+                q[2 * u] = w.x;
+                q[2 * u + 1] = w.y;
+            }
+        } else {
+            const lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+#pragma unroll
+            for (int k = 0; k < DC; ++k) q[k] = row[k * S];
+        }
+    };
+    auto row_store = [&](int j, const float (&q)[DC]) {
+        if constexpr (kPairs) {
+#pragma unroll
+            for (int u = 0; u < DC / 2; ++u) {
+                f32x2 w;
+                w.x = q[2 * u];
+                w.y = q[2 * u + 1];
+                *lds_ptr_f32x2(ibase_addr + 8u * ((uint32_t)(u * S) + (uint32_t)j)) = w;
+            }
+        } else {
+            lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
+#pragma unroll
+            for (int k = 0; k < DC; ++k) row[k * S] = q[k];
+        }
+    };
     // shared instances: the work item and two halting flags after the instance's LDS
     lds_u32 *ctl = lds_ptr_u32((uint32_t)(size_t)(lds_u8 *)smem + (uint32_t)a.inst_bytes);
     // the instance's phase boundary: its wavefronts' LDS writes seen by all of them
@@ -296,12 +330,13 @@ void bp_wave_kernel(BPArgs a) {
 #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = (sub * PC + c) * 64 + lane;
-                        lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
                         const uint32_t sg = ((sbits >> c) & 1u) << 31;
                         const float m = bitsf(fbits(a_first) | sg);
-                        row[0] = (DC == 8 && cwp[c] < 2u) ? bitsf(fbits(a_one) | sg) : m;
+                        float q[DC];
 #pragma unroll
-                        for (int k = 1; k < DC; ++k) row[k * S] = m;
+                        for (int k = 0; k < DC; ++k) q[k] = m;
+                        if (DC == 8 && cwp[c] < 2u) q[0] = bitsf(fbits(a_one) | sg);
+                        row_store(j, q);
                         *lds_ptr_u64(ibase_addr + LY::kDecOff + 8u * (uint32_t)j) = 0ull;
                     }
                     it = 1;
@@ -467,16 +502,13 @@ void bp_wave_kernel(BPArgs a) {
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = (sub * PC + c) * 64 + lane;
-                        const lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
-    #pragma unroll
-                        for (int k = 0; k < DC; ++k) qa[c][k] = row[k * S];
+                        row_load(j, qa[c]);
                         const uint64_t dw = *lds_ptr_u64(ibase_addr + LY::kDecOff + 8u * (uint32_t)j);
                         unsat |= (row_parity(dw) ^ (sbits >> c)) & ((rowv >> c) & 1u);
                     }
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
                         const int j = (sub * PC + c) * 64 + lane;
-                        lds_f32 *row = lds_ptr_f32(ibase_addr + 4u * (uint32_t)j);
                         float (&q)[DC] = qa[c];
                         if constexpr (DC == 8) {
                             const int w = (int)cwp[c];
@@ -498,8 +530,7 @@ void bp_wave_kernel(BPArgs a) {
                             }
                         } else {
                             CheckRule<RULE>::template apply<DC>(q, (int)((sbits >> c) & 1u), alpha, rmax);
-    #pragma unroll
-                            for (int k = 0; k < DC; ++k) row[k * S] = q[k];
+                            row_store(j, q);
                         }
                     }
                     // this wave's absent-edge words back to +0 for the next variable phase

@@ -330,6 +330,9 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
     const uint16_t sink = (uint16_t)(Mmax * 8);
     const bool paired = pair_hint && mbbp::bp_dual_fits(n, Mmax);
     const int lay_group = paired ? 16 : 32;  // variable slots per half-wave of one instance
+    // both flooding kernels keep messages in slot pairs, so the bank model is the
+    // slot-pair one either way (the serial and weighted forms, on plain slots, only
+    // see a layout tuned for the other addressing)
     P.voff.assign((size_t)L * n * 8, sink);
     P.vid.assign((size_t)L * n, 0);
     P.vdeg.assign((size_t)L * n, 0);
@@ -356,7 +359,7 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
             std::vector<std::vector<int>> rows(Ml);
             for (int j = 0; j < Ml; ++j) rows[j].assign(reps[l][j].begin(), reps[l][j].end());
             mbbp::layout::optimize(rows, n, Mmax, 0x5eed0000ull + (uint64_t)l * 7919u + (uint64_t)Mmax, iters,
-                                   lay, lay_group, lay_group, paired);
+                                   lay, lay_group, lay_group, true);
         }
         const std::vector<int32_t> &pos = lay.pos;
         // edges of every variable in ascending check order, as LDS edge ids pos * 8 + slot

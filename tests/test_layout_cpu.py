@@ -114,7 +114,7 @@ def test_layout_is_a_valid_permutation_keeping_pass_profiles(driver, G, B):
         assert sorted(deg[sv[p0:p0 + 2 * G]]) == sorted(deg[start[p0:p0 + 2 * G]])
 
 
-@pytest.mark.parametrize("G,B,pairs", [(32, 32, False), (16, 16, False), (16, 16, True)])
+@pytest.mark.parametrize("G,B,pairs", [(32, 32, False), (32, 32, True), (16, 16, False), (16, 16, True)])
 def test_layout_cost_is_the_bank_model_and_does_not_grow(driver, G, B, pairs):
     rows, n = representation(2)
     M = len(rows)
