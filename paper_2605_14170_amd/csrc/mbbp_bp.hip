@@ -172,6 +172,7 @@ void bp_wave_kernel(BPArgs a) {
     uint32_t cwp[PC];                // row weights (DC == 8 only)
     float mu[PV];
     int32_t csrcp[PC];               // syndrome source of each check position (kJunkRow: none)
+    uint32_t cpass_live = 0;         // bit c: check pass c holds a check of the representation
     // flooding min-sum / sum-product start every shot from stores only (iteration 0
     // needs no c->v message), so the LDS arrays are cleared only when a wave takes up
     // a representation; the weighted rule (damping reads r^(0) = 0) and the serial
@@ -235,10 +236,12 @@ void bp_wave_kernel(BPArgs a) {
                 }
             }
             const int32_t *csrc = pt->csrc + (size_t)l * Mmax;
+            cpass_live = 0;
 #pragma unroll
             for (int c = 0; c < PC; ++c) {
                 const int j = (sub * PC + c) * 64 + lane;
                 csrcp[c] = j < Mmax ? csrc[j] : kJunkRow;
+                if (__ballot(csrcp[c] != kJunkRow) != 0ull) cpass_live |= 1u << c;
             }
             clear_now = true;
             if constexpr (kKnownFirst) {
@@ -508,6 +511,8 @@ void bp_wave_kernel(BPArgs a) {
                     }
     #pragma unroll
                     for (int c = 0; c < PC; ++c) {
+                        // a pass without a check of this representation: nothing to compute
+                        if (!((cpass_live >> c) & 1u)) continue;
                         const int j = (sub * PC + c) * 64 + lane;
                         float (&q)[DC] = qa[c];
                         if constexpr (DC == 8) {

@@ -358,7 +358,10 @@ mbbp_status build_part(const std::vector<Row> &H, int n, const mbbp_basis_list &
         {
             std::vector<std::vector<int>> rows(Ml);
             for (int j = 0; j < Ml; ++j) rows[j].assign(reps[l][j].begin(), reps[l][j].end());
-            mbbp::layout::optimize(rows, n, Mmax, 0x5eed0000ull + (uint64_t)l * 7919u + (uint64_t)Mmax, iters,
+            // a representation's checks take the positions [0, Ml rounded up to a 64-lane
+            // check pass), so the flooding kernels skip the passes it leaves empty
+            const int npos = std::min(Mmax, (Ml + 63) / 64 * 64);
+            mbbp::layout::optimize(rows, n, npos, 0x5eed0000ull + (uint64_t)l * 7919u + (uint64_t)Mmax, iters,
                                    lay, lay_group, lay_group, true);
         }
         const std::vector<int32_t> &pos = lay.pos;
