@@ -26,13 +26,17 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # messages are never NaN, no result changes).  Not for the host file, whose argument
 # checks must still see NaN.
 KERNEL_ONLY = ["-mno-amdgpu-ieee", "-fno-honor-nans"]
+# The paired BP kernel: branches on wave-uniform values (a pass's largest degree) are
+# left as scalar branches rather than rewritten into structured flow with flag
+# registers, which cost the variable phase a dozen scalar instructions per pass.
+PER_SOURCE = {"mbbp_bp_dual.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
 SOURCES = ["mbbp_bp.hip", "mbbp_bp_dual.hip", "mbbp_bp_serial.hip", "mbbp_bp_serial_slots.hip", "mbbp_wbp.hip",
            "mbbp_kernels.hip", "mbbp_host.cpp"]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE, *KERNEL_ONLY, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *DEVICE, *KERNEL_ONLY, *PER_SOURCE.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *COMMON, "-x", "hip", *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)

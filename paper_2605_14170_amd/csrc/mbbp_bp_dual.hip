@@ -315,27 +315,45 @@ void bp_dual_kernel(BPArgs a) {
             for (int v = 0; v < PV2; ++v)
 #pragma unroll
                 for (int k = 0; k < MAXD; ++k) asm volatile("" : "+v"(ea[v][k]));
+            // Every lane runs every pass: a lane past the last variable has a 0 prior and
+            // only absent edges, so it reads +0, writes its pass's absent-edge word (zeroed
+            // again before it is read) and keeps decision 0.  The code of each degree is
+            // then free of lane-dependent branches; the decision cells (absent edges: those
+            // of the unused position) are stored after it, by the lanes whose decision
+            // changed.
 #pragma unroll
             for (int v = 0; v < PV2; ++v) {
-                if (v * 32 + half < n) {
-                    const int deg = (int)(vinfo[v] >> 16);
-                    float Pv = 0.0f;
-                    bool d = false;
-                    const bool prevd = (decb >> v) & 1u;
-                    switch (uniform_i32(dmaxp[v])) {
-                    case 1: var_rule<1, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 2: var_rule<2, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 3: var_rule<3, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 4: if constexpr (MAXD >= 4) var_rule<4, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 5: if constexpr (MAXD >= 5) var_rule<5, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 6: if constexpr (MAXD >= 6) var_rule<6, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 7: if constexpr (MAXD >= 7) var_rule<7, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    case 8: if constexpr (MAXD >= 8) var_rule<8, LY, true>(ea[v], deg, mu[v], prevd, Pv, d); break;
-                    default: Pv = mu[v]; d = Pv < 0.0f; break;
-                    }
-                    decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
-                    if constexpr (RICH) Pl[v] = Pv;
+                float Pv;
+                switch (uniform_i32(dmaxp[v])) {
+                case 1: Pv = var_msgs<1, LY>(ea[v], mu[v]); break;
+                case 2: Pv = var_msgs<2, LY>(ea[v], mu[v]); break;
+                case 3: Pv = var_msgs<3, LY>(ea[v], mu[v]); break;
+                case 4: if constexpr (MAXD >= 4) Pv = var_msgs<4, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
+                case 5: if constexpr (MAXD >= 5) Pv = var_msgs<5, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
+                case 6: if constexpr (MAXD >= 6) Pv = var_msgs<6, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
+                case 7: if constexpr (MAXD >= 7) Pv = var_msgs<7, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
+                case 8: if constexpr (MAXD >= 8) Pv = var_msgs<8, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
+                default: Pv = mu[v]; break;
                 }
+                const bool d = Pv < 0.0f;
+                if (d != (bool)((decb >> v) & 1u)) {
+                    // slots below the pass's largest degree (a higher slot is absent in every
+                    // lane: stores there would all meet at one byte)
+                    const unsigned char db = (unsigned char)d;
+                    switch (uniform_i32(dmaxp[v])) {
+                    case 8: if constexpr (MAXD >= 8) *lds_ptr_u8(LY::dec(ea[v][7])) = db; [[fallthrough]];
+                    case 7: if constexpr (MAXD >= 7) *lds_ptr_u8(LY::dec(ea[v][6])) = db; [[fallthrough]];
+                    case 6: if constexpr (MAXD >= 6) *lds_ptr_u8(LY::dec(ea[v][5])) = db; [[fallthrough]];
+                    case 5: if constexpr (MAXD >= 5) *lds_ptr_u8(LY::dec(ea[v][4])) = db; [[fallthrough]];
+                    case 4: if constexpr (MAXD >= 4) *lds_ptr_u8(LY::dec(ea[v][3])) = db; [[fallthrough]];
+                    case 3: *lds_ptr_u8(LY::dec(ea[v][2])) = db; [[fallthrough]];
+                    case 2: *lds_ptr_u8(LY::dec(ea[v][1])) = db; [[fallthrough]];
+                    case 1: *lds_ptr_u8(LY::dec(ea[v][0])) = db; break;
+                    default: break;
+                    }
+                }
+                decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
+                if constexpr (RICH) Pl[v] = Pv;
             }
             wave_sync();
             // ---------------- check phase: syndrome test and c->v messages

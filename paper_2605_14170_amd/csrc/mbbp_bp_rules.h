@@ -324,6 +324,23 @@ __device__ __forceinline__ void var_rule(const uint32_t *ea, int deg, float mu, 
     }
 }
 
+// The message part of the variable rule for a degree <= D whose absent edges read +0
+// (the ZSINK form above): loads, exclusion sums and the stores of every q_k; returns
+// the posterior.  The caller stores the hard decision, so that the code of one degree
+// holds no lane-dependent branch.
+template <int D, typename LY>
+__device__ __forceinline__ float var_msgs(const uint32_t *ea, float mu) {
+    constexpr uint32_t ROFF = LY::kROff;
+    float r[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) r[k] = *lds_ptr_f32(LY::msg(ea[k]) + ROFF);
+    float q[D];
+    const float pre = excl_sums<D>(r, mu, q);
+#pragma unroll
+    for (int k = 0; k < D; ++k) *lds_ptr_f32(LY::msg(ea[k])) = q[k];
+    return pre;
+}
+
 // Variable rule at iteration 0 of the flooding schedule, where every c->v message is
 // 0: q_k = P = mu (stored as-is; mu is canonical, never -0), and every decision cell
 // is written, so nothing left from an earlier shot is read later.
