@@ -324,16 +324,28 @@ void bp_dual_kernel(BPArgs a) {
 #pragma unroll
             for (int v = 0; v < PV2; ++v) {
                 float Pv;
-                switch (uniform_i32(dmaxp[v])) {
+                // degrees 3 and 4 (most passes of codes with column weight 3) are tested
+                // first, each by one compare; the opaque copy keeps the compiler from
+                // merging the tests into one balanced search over all degrees
+                int dm = uniform_i32(dmaxp[v]);
+                if (dm == 3) {
+                    Pv = var_msgs<3, LY>(ea[v], mu[v]);
+                } else {
+                asm volatile("" : "+s"(dm));
+                if (dm == 4) {
+                    if constexpr (MAXD >= 4) Pv = var_msgs<4, LY>(ea[v], mu[v]); else Pv = mu[v];
+                } else {
+                asm volatile("" : "+s"(dm));
+                switch (dm) {
                 case 1: Pv = var_msgs<1, LY>(ea[v], mu[v]); break;
                 case 2: Pv = var_msgs<2, LY>(ea[v], mu[v]); break;
-                case 3: Pv = var_msgs<3, LY>(ea[v], mu[v]); break;
-                case 4: if constexpr (MAXD >= 4) Pv = var_msgs<4, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
                 case 5: if constexpr (MAXD >= 5) Pv = var_msgs<5, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
                 case 6: if constexpr (MAXD >= 6) Pv = var_msgs<6, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
                 case 7: if constexpr (MAXD >= 7) Pv = var_msgs<7, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
                 case 8: if constexpr (MAXD >= 8) Pv = var_msgs<8, LY>(ea[v], mu[v]); else Pv = mu[v]; break;
                 default: Pv = mu[v]; break;
+                }
+                }
                 }
                 const bool d = Pv < 0.0f;
                 if (d != (bool)((decb >> v) & 1u)) {
