@@ -351,17 +351,21 @@ void bp_dual_kernel(BPArgs a) {
                 if (d != (bool)((decb >> v) & 1u)) {
                     // slots below the pass's largest degree (a higher slot is absent in every
                     // lane: stores there would all meet at one byte)
+                    // (slots 0..2 first: most passes have degree 3 or more)
                     const unsigned char db = (unsigned char)d;
-                    switch (uniform_i32(dmaxp[v])) {
-                    case 8: if constexpr (MAXD >= 8) *lds_ptr_u8(LY::dec(ea[v][7])) = db; [[fallthrough]];
-                    case 7: if constexpr (MAXD >= 7) *lds_ptr_u8(LY::dec(ea[v][6])) = db; [[fallthrough]];
-                    case 6: if constexpr (MAXD >= 6) *lds_ptr_u8(LY::dec(ea[v][5])) = db; [[fallthrough]];
-                    case 5: if constexpr (MAXD >= 5) *lds_ptr_u8(LY::dec(ea[v][4])) = db; [[fallthrough]];
-                    case 4: if constexpr (MAXD >= 4) *lds_ptr_u8(LY::dec(ea[v][3])) = db; [[fallthrough]];
-                    case 3: *lds_ptr_u8(LY::dec(ea[v][2])) = db; [[fallthrough]];
-                    case 2: *lds_ptr_u8(LY::dec(ea[v][1])) = db; [[fallthrough]];
-                    case 1: *lds_ptr_u8(LY::dec(ea[v][0])) = db; break;
-                    default: break;
+                    int dd = uniform_i32(dmaxp[v]);
+                    if (dd >= 3) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) *lds_ptr_u8(LY::dec(ea[v][k])) = db;
+#pragma unroll
+                        for (int k = 3; k < MAXD; ++k) {
+                            asm volatile("" : "+s"(dd));
+                            if (dd <= k) break;
+                            *lds_ptr_u8(LY::dec(ea[v][k])) = db;
+                        }
+                    } else {
+                        if (dd >= 1) *lds_ptr_u8(LY::dec(ea[v][0])) = db;
+                        if (dd >= 2) *lds_ptr_u8(LY::dec(ea[v][1])) = db;
                     }
                 }
                 decb = (decb & ~(1u << v)) | ((uint32_t)d << v);
