@@ -26,10 +26,11 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # messages are never NaN, no result changes).  Not for the host file, whose argument
 # checks must still see NaN.
 KERNEL_ONLY = ["-mno-amdgpu-ieee", "-fno-honor-nans"]
-# The paired BP kernel: branches on wave-uniform values (a pass's largest degree) are
-# left as scalar branches rather than rewritten into structured flow with flag
+# The flooding BP kernels: branches on wave-uniform values (a pass's largest degree)
+# are left as scalar branches rather than rewritten into structured flow with flag
 # registers, which cost the variable phase a dozen scalar instructions per pass.
-PER_SOURCE = {"mbbp_bp_dual.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+UNIFORM_BRANCHES = ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
+PER_SOURCE = {"mbbp_bp_dual.hip": UNIFORM_BRANCHES, "mbbp_bp.hip": UNIFORM_BRANCHES}
 SOURCES = ["mbbp_bp.hip", "mbbp_bp_dual.hip", "mbbp_bp_serial.hip", "mbbp_bp_serial_slots.hip", "mbbp_wbp.hip",
            "mbbp_kernels.hip", "mbbp_host.cpp"]
 
